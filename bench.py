@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Throughput of the particle forward map on one MI355X.
+
+One benchmark step is one evaluation of G(u) (Algorithm 1) on the main torus
+workload: 49 observation points on a 7x7 grid, 1e5 particles each, 1000
+Euler-Maruyama steps (T = 1, dt = 1e-3), a stream function with 168 Fourier
+coefficients (|k|_inf <= 6), FP32 particle states with FP64 payoffs and
+statistics -- 4.9e9 particle-steps per step.  Inputs are seeded synthetic
+draws; u and the observation points are resident in HBM before timing, and
+each step ends when the 49 means are back on the host (as an MCMC step needs).
+
+Prints one JSON line:
+  value            particle-steps/s over the K timed steps (wall clock)
+  roofline         the time kernel's FP32 FLOP rate from HIP events on its
+                   stream against the chip's FP32 vector peak
+  cpu_baseline     the FP64 CPU oracle on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector (packed) peak
+PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
+
+
+def flops_per_particle_step(K: int) -> int:
+    """Algorithmic FP32 FLOPs of one Euler-Maruyama step of the time kernel
+    (FMA = 2).  Trig basis: per axis K-1 angle-addition harmonics of 2 mul +
+    2 FMA.  Velocity: two bilinear forms phi(x)^T C phi(y) over B = 2K+1
+    basis functions per axis; row j = 0 carries only the y form (1 mul +
+    (B-2) FMA), rows j >= 1 carry both (x: B-1 FMA, y: 1 mul + B-2 FMA) and
+    two FMAs into (v_x, v_y).  Update: 1 add + 2 FMA per axis.  Box-Muller
+    arithmetic: 1 FMA + 4 mul per normal pair.  The 8 hardware
+    transcendentals and the Philox integer work are not counted."""
+    B = 2 * K + 1
+    basis = 2 * (K - 1) * (2 * 1 + 2 * 2)
+    row0 = 1 + 2 * (B - 2)
+    row = 2 * (B - 1) + (1 + 2 * (B - 2)) + 2 * 2
+    contraction = row0 + (B - 1) * row
+    update = 2 * (1 + 2 * 2)
+    bm = 2 + 4
+    return basis + contraction + update + bm
+
+
+def cpu_baseline(wl, n_particles: int):
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    oracle.observe_time(wl.modes, wl.u, wl.theta0, wl.obs, wl.kappa, wl.T, wl.dt, n_particles, wl.seed)
+    dt = time.perf_counter() - t0
+    steps = wl.n_obs * n_particles * wl.n_steps
+    return {"value": steps / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{wl.n_obs} points x {n_particles} particles x {wl.n_steps} steps "
+                      f"({steps:.3g} particle-steps, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-particles", type=int, default=400,
+                    help="particles per point in the oracle's CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ppl", type=int, default=0, help="particles per lane (0 = library default)")
+    ap.add_argument("--coef-source", type=int, default=0, help="0 = LDS, 1 = scalar cache")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the particle map's "
+              "multi-GPU sharding is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1808_10580_amd as pm
+    import workloads as W
+
+    wl = W.time_main()
+    dev = torch.device("cuda", 0)
+    ctx = pm.Context(0)
+    ctx.set_tuning(args.ppl, args.coef_source)
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+    u = torch.tensor(wl.u, dtype=torch.float64, device=dev)
+    obs = torch.tensor(wl.obs, dtype=torch.float64, device=dev)
+    K = int(abs(wl.modes).max())
+    steps_per_map = wl.n_obs * wl.n_particles * wl.n_steps
+
+    def one_map():
+        m, v = prob.observe_time(u, obs, wl.kappa, wl.T, wl.dt, wl.n_particles, wl.seed)
+        host = m.cpu()  # the step ends with G(u) on the host
+        st = ctx.sync()
+        if st != pm.PM_OK:
+            raise pm.PMError(st, "forward map")
+        return host
+
+    for _ in range(args.warmup):
+        one_map()
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_map()
+        kernel_ms.append(ctx.last_kernel_stats()[0])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = steps_per_map * args.steps / elapsed
+    print(f"[bench] {args.steps} maps in {elapsed:.3f} s; time kernel {min(kernel_ms):.2f}-"
+          f"{max(kernel_ms):.2f} ms", file=sys.stderr)
+
+    fl = flops_per_particle_step(K)
+    kern_s = sum(kernel_ms) / len(kernel_ms) / 1e3
+    achieved = fl * steps_per_map / kern_s / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": "k_time<float,6>", "kernel_ms": round(kern_s * 1e3, 3),
+                "flop_per_particle_step": fl,
+                "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+                "frac_unpacked": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, args.cpu_particles)
+
+    out = {
+        "metric": "particle-steps/s at 1 GPU",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "torus-k6-fp32: 2D torus, |k|_inf<=6 stream function (168 coefficients), "
+                               "kappa=0.01, theta0 = 3 periodised Gaussian bumps, 7x7 grid x 1e5 particles, "
+                               "T=1, dt=1e-3 (1000 steps), FP32 states + FP64 statistics",
+                   "particle_steps_per_step": steps_per_map},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * pm.h -- C ABI of the MI355X (gfx950) particle forward-map library libpm.so.
+ *
+ * The library evaluates the forward map G(u) = {G_j(u)} of the paper's
+ * Problems 2.1 and 2.2 (eq. Gmap) with the particle methods of Section 3:
+ * Algorithm 1 (time-dependent advection-diffusion, Theorem 3.1) and
+ * Algorithm 2 (Dirichlet boundary-value problem, Theorem 3.2), for the
+ * constant-diffusion, divergence-free setting of Section 4.1 (eq. adr,
+ * sigma = sqrt(2 kappa) I, velocity of eq. v_expand).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - The unknown u is the stream function
+ *       psi(x) = sum_m a_m cos(2 pi k_m.x) + b_m sin(2 pi k_m.x),
+ *   stored as u = [a_0..a_{M-1}, b_0..b_{M-1}] (FP64) in the order of the
+ *   wavevector table given to pm_problem_create; the velocity is
+ *       v = (d psi/dy, -d psi/dx) + v0,
+ *   which is eq. v_expand with v_k = -pi |k| (b_k + i a_k).  On the unit disk
+ *   psi is multiplied by the cutoff (1 - |x|^2)^2 before differentiating.
+ * - Particle paths follow eq. (euler) with uniform steps:
+ *       X_{n+1} = X_n - v(X_n) dt + sqrt(2 kappa dt) xi_n,
+ *   wrapped to [0,1)^2 on the torus.  (Milstein, eq. millstein, is the same
+ *   map for constant sigma.)
+ * - xi_n comes from Philox4x32-10 (Salmon et al., SC'11) with
+ *       key = (seed lo32, seed hi32), counter = (n/2, i, j, 0),
+ *   words (w0,w1) for even n and (w2,w3) for odd n, uniforms
+ *   ua = ((wa>>8)+1) 2^-24, ub = (wb>>8) 2^-24, and Box-Muller
+ *   xi = sqrt(-2 ln ua) (cos 2 pi ub, sin 2 pi ub).  i is the particle index
+ *   within observation j, so any path can be replayed from (seed, j, i).
+ * - All array arguments marked "device" are device pointers on the context's
+ *   device (for example torch tensors' data_ptr()).  Arguments marked "host"
+ *   are host pointers read before the call returns.  The caller owns every
+ *   buffer; the library owns only the internals of pm_ctx and pm_problem.
+ * - Calls enqueue work on the context's stream and return; device results
+ *   are valid after pm_sync() (or after synchronising that stream).
+ * - Argument errors are detected before any launch and return PM_EINVAL
+ *   without side effects.  No call throws across the ABI.
+ * - A context is not thread safe: use one per host thread.
+ * - FP32 problems keep particle states and the velocity basis in FP32 and
+ *   every payoff, exit projection, source integral and mean/variance
+ *   accumulation in FP64.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pm_ctx pm_ctx;
+typedef struct pm_problem pm_problem;
+
+enum pm_status {
+    PM_OK = 0,
+    PM_EINVAL = -1,       /* bad argument; nothing was launched */
+    PM_ENOMEM = -2,       /* device allocation failed */
+    PM_EDEVICE = -3,      /* HIP runtime error (launch or sync) */
+    PM_ENONFINITE = -4,   /* (pm_sync) a payoff was NaN/Inf */
+    PM_ECAPPED = -5,      /* (pm_sync) a Dirichlet path hit max_steps */
+    PM_EUNSUPPORTED = -6  /* valid request outside the compiled kernel set */
+};
+
+enum pm_domain { PM_TORUS = 0, PM_DISK = 1 };
+enum pm_prec { PM_FP32 = 0, PM_FP64 = 1 };
+
+/* Scalar fields theta0 (initial condition), theta_dD (boundary data) and
+ * f (source).  params is a host array of n_params doubles (n_params <= 32).
+ *   PM_F_ZERO            0
+ *   PM_F_CONST           c                                       [c]
+ *   PM_F_SINSIN          A sin(2 pi x) sin(2 pi y)               [A]
+ *   PM_F_FOURIER         sum c cos 2pi(px+qy) + d sin 2pi(px+qy) [p,q,c,d]*n
+ *   PM_F_GAUSS_PERIODIC  sum A sum_{n in {-1,0,1}^2} exp(-|x-c-n|^2/(2 s^2))  [cx,cy,s,A]*n
+ *   PM_F_COS_M_THETA     cos(m atan2(y,x))                       [m]
+ *   PM_F_EXP_LINEAR      exp(c0 x + c1 y)                        [c0,c1]
+ *   PM_F_LINEAR          c0 x + c1 y + c2                        [c0,c1,c2]
+ */
+enum pm_field_kind {
+    PM_F_ZERO = 0, PM_F_CONST = 1, PM_F_SINSIN = 2, PM_F_FOURIER = 3,
+    PM_F_GAUSS_PERIODIC = 4, PM_F_COS_M_THETA = 5, PM_F_EXP_LINEAR = 6, PM_F_LINEAR = 7
+};
+#define PM_FIELD_MAX_PARAMS 32
+
+typedef struct {
+    int32_t kind;
+    int32_t n_params;
+    const double *params; /* host */
+} pm_field;
+
+/* Largest |k_x|, |k_y| of a wavevector table that the compiled kernels accept. */
+#define PM_MAX_K 8
+
+/* Create a context on HIP device `device` that enqueues on `stream`
+ * (a hipStream_t; NULL = the null stream).  Returns PM_OK, PM_EINVAL or
+ * PM_EDEVICE. */
+int pm_create(pm_ctx **out, int device, void *stream);
+void pm_destroy(pm_ctx *ctx);
+/* Re-bind the context to another stream of the same device. */
+int pm_set_stream(pm_ctx *ctx, void *stream);
+
+/* Problem handle: what a chain or an optimiser does not vary.
+ *   domain   PM_TORUS (Problem 2.1 on [0,1)^2) or PM_DISK (Problem 2.2 on
+ *            the unit disk)
+ *   n_modes  M >= 0, k: host [M][2] int32 wavevectors, |k_x|,|k_y| <= PM_MAX_K
+ *   v0       host [2] constant drift added to the Fourier field, or NULL
+ *   theta0   host initial condition for pm_observe_time (NULL for PM_DISK)
+ *   prec     PM_FP32 or PM_FP64 particle arithmetic
+ * The table and theta0 are copied; the caller's arrays may be freed. */
+int pm_problem_create(pm_ctx *ctx, pm_problem **out, int domain, int n_modes,
+                      const int32_t *k, const double *v0, const pm_field *theta0, int prec);
+void pm_problem_destroy(pm_problem *p);
+
+/* Algorithm 1 (Section 3.1): G_j(u) = theta(T, x_j) ~ mean_i theta0(X_T^(i)).
+ *   u         device [2M] FP64
+ *   obs_pts   device [n_obs][2] FP64 observation points x_j
+ *   kappa>=0, T>0, dt>0: N_t = ceil(T/dt) steps of size T/N_t
+ *   n_particles >= 1 particles per observation, seed = Philox key
+ *   mean, var device [n_obs] FP64: sample mean and unbiased sample variance
+ *             of the payoffs theta0(X_T) (standard error = sqrt(var/Np))
+ *   endpoints device [n_obs][n_particles][2] FP64 X_T per path, or NULL
+ * Requires a PM_TORUS problem with theta0. */
+int pm_observe_time(pm_ctx *ctx, const pm_problem *p, const double *u, const double *obs_pts,
+                    int n_obs, double kappa, double T, double dt, int64_t n_particles,
+                    uint64_t seed, double *mean, double *var, double *endpoints);
+
+/* Algorithm 2 (Section 3.2, Theorem 3.2) on the unit disk:
+ *   payoff_i = theta_dD(X_tau) - int_0^tau f(X_t) dt
+ * with the exit detected when |Y|^2 >= 1 after a step (tested in FP64), the
+ * exit point projected radially onto the circle (FP64), tau = n dt for the
+ * first outside step n and the source integrated by the left-point rule in
+ * FP64.  A path still inside after max_steps steps is capped: its payoff is
+ * -int f (no boundary term), it is counted in n_capped and pm_sync() returns
+ * PM_ECAPPED.
+ *   f, g      host field descriptors (source and boundary data)
+ *   mean,var  device [n_obs] payoff statistics
+ *   tau_mean, tau_var device [n_obs] exit-time statistics (time units)
+ *   n_capped  device [n_obs] int64
+ *   paths     device [n_obs][n_particles][4] FP64 (exit x, exit y, payoff,
+ *             exit step) per path, or NULL */
+int pm_observe_dirichlet(pm_ctx *ctx, const pm_problem *p, const double *u, const pm_field *f,
+                         const pm_field *g, const double *obs_pts, int n_obs, double kappa,
+                         double dt, int64_t n_particles, uint64_t seed, int64_t max_steps,
+                         double *mean, double *var, double *tau_mean, double *tau_var,
+                         int64_t *n_capped, double *paths);
+
+/* Many parameter sets in one persistent launch (the same G of Algorithm 1 for
+ * each u_b, each with its own particle count and seed).  Results are bitwise
+ * equal to n_u separate pm_observe_time calls with the same arguments.
+ *   u            device [n_u][2M] FP64
+ *   n_particles  host [n_u] int64 (>= 1), seeds host [n_u]
+ *   mean, var    device [n_u][n_obs] FP64 */
+int pm_observe_time_batch(pm_ctx *ctx, const pm_problem *p, int n_u, const double *u,
+                          const int64_t *n_particles, const uint64_t *seeds,
+                          const double *obs_pts, int n_obs, double kappa, double T, double dt,
+                          double *mean, double *var);
+
+/* One Euler-Maruyama step per entry (eq. euler), for replaying or checking
+ * paths: Y[e] = step n[e] of particle (i[e], j[e]) applied to X[e], in the
+ * problem's precision (X is rounded to it first).  Device arrays:
+ *   X, Y [count][2] FP64, n [count] uint64, i, j [count] uint32. */
+int pm_step(pm_ctx *ctx, const pm_problem *p, const double *u, int64_t count, const double *X,
+            const uint64_t *n, const uint32_t *i, const uint32_t *j, double kappa, double dt,
+            uint64_t seed, double *Y);
+
+/* Velocity v(X) (eq. v_expand plus v0, with the disk cutoff) at count points
+ * in the problem's precision.  Device X, V [count][2] FP64. */
+int pm_velocity(pm_ctx *ctx, const pm_problem *p, const double *u, int64_t count,
+                const double *X, double *V);
+
+/* Normal pairs xi_n of particle (i, j) in the problem's precision.  Device
+ * n [count] uint64, i, j [count] uint32, Z [count][2] FP64. */
+int pm_normals(pm_ctx *ctx, const pm_problem *p, int64_t count, const uint64_t *n,
+               const uint32_t *i, const uint32_t *j, uint64_t seed, double *Z);
+
+/* Wait for the context's stream.  Returns PM_EDEVICE on a runtime error,
+ * else PM_ENONFINITE / PM_ECAPPED if a call since the previous pm_sync saw
+ * a non-finite payoff or a capped path, else PM_OK.  Clears the flags. */
+int pm_sync(pm_ctx *ctx);
+
+/* Time of the last kernel of the most recent observe call, measured with
+ * HIP events on the context's stream (milliseconds), and the number of
+ * particle-steps it executed.  Valid after pm_sync(). */
+int pm_last_kernel_stats(pm_ctx *ctx, double *ms, double *particle_steps);
+
+const char *pm_strerror(int status);
+
+/* Kernel tuning knob for the time kernel: particles per lane (1, 2 or 4) and
+ * coefficient source (0 = LDS, 1 = scalar cache); 0 = library default. */
+int pm_set_tuning(pm_ctx *ctx, int particles_per_lane, int coef_source);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PM_H */

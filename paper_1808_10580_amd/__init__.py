@@ -1,0 +1,303 @@
+"""MI355X (gfx950) particle forward maps for sparse-observation inverse problems.
+
+Thin ctypes binding of libpm.so (C ABI in include/pm.h).  Every step of the
+path runs in the library's HIP kernels; this module only marshals arguments:
+torch CUDA tensors provide device memory and the current HIP stream.
+
+The library must be built in-tree first (``python -m paper_1808_10580_amd.build``
+or ``__graft_entry__.build()``); importing a function that needs it raises if
+libpm.so is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpm.so")
+
+PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_ENONFINITE, PM_ECAPPED, PM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+TORUS, DISK = 0, 1
+FP32, FP64 = 0, 1
+FIELD_KINDS = {"zero": 0, "const": 1, "sinsin": 2, "fourier": 3, "gauss_periodic": 4,
+               "cos_m_theta": 5, "exp_linear": 6, "linear": 7}
+MAX_K = 8
+
+
+class PMError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = _lib().pm_strerror(status).decode() if _LIBH is not None else str(status)
+        super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
+
+
+_LIBH = None
+
+
+class _Field(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_params", C.c_int32), ("params", C.POINTER(C.c_double))]
+
+
+_vp = C.c_void_p
+_d = C.c_double
+_i64 = C.c_int64
+_u64 = C.c_uint64
+
+
+def _declare(L):
+    L.pm_strerror.restype = C.c_char_p
+    L.pm_strerror.argtypes = [C.c_int]
+    L.pm_create.argtypes = [C.POINTER(_vp), C.c_int, _vp]
+    L.pm_destroy.argtypes = [_vp]
+    L.pm_destroy.restype = None
+    L.pm_set_stream.argtypes = [_vp, _vp]
+    L.pm_set_tuning.argtypes = [_vp, C.c_int, C.c_int]
+    L.pm_problem_create.argtypes = [_vp, C.POINTER(_vp), C.c_int, C.c_int, _vp, _vp,
+                                    C.POINTER(_Field), C.c_int]
+    L.pm_problem_destroy.argtypes = [_vp]
+    L.pm_problem_destroy.restype = None
+    L.pm_observe_time.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _d, _i64, _u64, _vp, _vp, _vp]
+    L.pm_observe_time_batch.argtypes = [_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.c_int, _d, _d, _d,
+                                        _vp, _vp]
+    L.pm_observe_dirichlet.argtypes = [_vp, _vp, _vp, C.POINTER(_Field), C.POINTER(_Field), _vp,
+                                       C.c_int, _d, _d, _i64, _u64, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.pm_step.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _d, _d, _u64, _vp]
+    L.pm_velocity.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp]
+    L.pm_normals.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp, _u64, _vp]
+    L.pm_sync.argtypes = [_vp]
+    L.pm_last_kernel_stats.argtypes = [_vp, C.POINTER(_d), C.POINTER(_d)]
+    for name in ("pm_graph_create", "pm_graph_launch", "pm_graph_destroy"):
+        if hasattr(L, name):
+            pass
+    return L
+
+
+def _lib():
+    global _LIBH
+    if _LIBH is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1808_10580_amd.build`")
+        _LIBH = _declare(C.CDLL(LIB_PATH))
+    return _LIBH
+
+
+def lib():
+    """The loaded libpm.so (ctypes handle)."""
+    return _lib()
+
+
+def _check(st: int, what: str):
+    if st != PM_OK:
+        raise PMError(st, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(x, dtype, device):
+    torch = _torch()
+    if isinstance(x, torch.Tensor):
+        t = x.to(device=device, dtype=dtype)
+    else:
+        t = torch.as_tensor(np.asarray(x), dtype=dtype, device=device)
+    return t.contiguous()
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class _FieldHolder:
+    def __init__(self, fd: Optional[dict]):
+        if fd is None:
+            fd = {"kind": "zero", "params": []}
+        p = np.ascontiguousarray(np.asarray(fd.get("params", []), dtype=np.float64).reshape(-1))
+        self.p = p if p.size else np.zeros(1)
+        self.s = _Field(FIELD_KINDS[fd["kind"]], int(p.size),
+                        self.p.ctypes.data_as(C.POINTER(C.c_double)))
+
+
+class Context:
+    """A libpm context bound to a HIP device; calls enqueue on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        st = _lib().pm_create(C.byref(h), device, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+        _check(st, "pm_create")
+        self.h = h
+
+    def bind_stream(self):
+        torch = _torch()
+        _lib().pm_set_stream(self.h, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def set_tuning(self, particles_per_lane: int = 0, coef_source: int = 0):
+        _check(_lib().pm_set_tuning(self.h, particles_per_lane, coef_source), "pm_set_tuning")
+
+    def sync(self, raise_on_flags: bool = False) -> int:
+        st = _lib().pm_sync(self.h)
+        if st in (PM_EDEVICE, PM_EINVAL) or (raise_on_flags and st != PM_OK):
+            raise PMError(st, "pm_sync")
+        return st
+
+    def last_kernel_stats(self):
+        ms, steps = C.c_double(), C.c_double()
+        _check(_lib().pm_last_kernel_stats(self.h, C.byref(ms), C.byref(steps)), "pm_last_kernel_stats")
+        return ms.value, steps.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib().pm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """Problem handle: domain, wavevector table, constant drift, theta0, precision."""
+
+    def __init__(self, ctx: Context, domain: str, modes, v0=(0.0, 0.0), theta0: Optional[dict] = None,
+                 prec: str = "fp32"):
+        self.ctx = ctx
+        self.modes = np.ascontiguousarray(np.asarray(modes, dtype=np.int32).reshape(-1, 2))
+        self.n_modes = int(self.modes.shape[0])
+        self.domain = domain
+        self.prec = prec
+        v0a = np.ascontiguousarray(np.asarray(v0, dtype=np.float64).reshape(2))
+        th = _FieldHolder(theta0) if theta0 is not None else None
+        h = C.c_void_p()
+        st = _lib().pm_problem_create(
+            ctx.h, C.byref(h), {"torus": TORUS, "disk": DISK}[domain], self.n_modes,
+            C.c_void_p(self.modes.ctypes.data) if self.n_modes else None, C.c_void_p(v0a.ctypes.data),
+            C.byref(th.s) if th is not None else None, {"fp32": FP32, "fp64": FP64}[prec])
+        _check(st, "pm_problem_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib().pm_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _u(self, u):
+        torch = _torch()
+        t = _dev(u, torch.float64, self.ctx.device)
+        return t
+
+    # -- Algorithm 1 -----------------------------------------------------------------
+    def observe_time(self, u, obs, kappa, T, dt, n_particles, seed, endpoints=False):
+        """G_j(u) of Algorithm 1: (mean, var[, endpoints]) as CUDA float64 tensors."""
+        torch = _torch()
+        self.ctx.bind_stream()
+        ut = self._u(u)
+        ob = _dev(obs, torch.float64, self.ctx.device).reshape(-1, 2)
+        n_obs = ob.shape[0]
+        mean = torch.empty(n_obs, dtype=torch.float64, device=self.ctx.device)
+        var = torch.empty_like(mean)
+        ep = (torch.empty((n_obs, int(n_particles), 2), dtype=torch.float64, device=self.ctx.device)
+              if endpoints else None)
+        st = _lib().pm_observe_time(self.ctx.h, self.h, _ptr(ut), _ptr(ob), n_obs, float(kappa), float(T),
+                                    float(dt), int(n_particles), int(seed), _ptr(mean), _ptr(var), _ptr(ep))
+        _check(st, "pm_observe_time")
+        return (mean, var, ep) if endpoints else (mean, var)
+
+    def observe_time_batch(self, U, n_particles: Sequence[int], seeds: Sequence[int], obs, kappa, T, dt):
+        torch = _torch()
+        self.ctx.bind_stream()
+        Ut = _dev(U, torch.float64, self.ctx.device).reshape(-1, 2 * self.n_modes if self.n_modes else 0)
+        n_u = int(len(n_particles))
+        ob = _dev(obs, torch.float64, self.ctx.device).reshape(-1, 2)
+        n_obs = ob.shape[0]
+        nps = np.ascontiguousarray(np.asarray(n_particles, dtype=np.int64))
+        sds = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+        mean = torch.empty((n_u, n_obs), dtype=torch.float64, device=self.ctx.device)
+        var = torch.empty_like(mean)
+        st = _lib().pm_observe_time_batch(self.ctx.h, self.h, n_u, _ptr(Ut), C.c_void_p(nps.ctypes.data),
+                                          C.c_void_p(sds.ctypes.data), _ptr(ob), n_obs, float(kappa),
+                                          float(T), float(dt), _ptr(mean), _ptr(var))
+        _check(st, "pm_observe_time_batch")
+        return mean, var
+
+    # -- Algorithm 2 -----------------------------------------------------------------
+    def observe_dirichlet(self, u, f: dict, g: dict, obs, kappa, dt, n_particles, seed, max_steps,
+                          paths=False):
+        torch = _torch()
+        self.ctx.bind_stream()
+        ut = self._u(u)
+        ob = _dev(obs, torch.float64, self.ctx.device).reshape(-1, 2)
+        n_obs = ob.shape[0]
+        dev = self.ctx.device
+        out = {k: torch.empty(n_obs, dtype=torch.float64, device=dev)
+               for k in ("mean", "var", "tau_mean", "tau_var")}
+        out["n_capped"] = torch.empty(n_obs, dtype=torch.int64, device=dev)
+        pt = (torch.empty((n_obs, int(n_particles), 4), dtype=torch.float64, device=dev) if paths else None)
+        ff, gg = _FieldHolder(f), _FieldHolder(g)
+        st = _lib().pm_observe_dirichlet(self.ctx.h, self.h, _ptr(ut), C.byref(ff.s), C.byref(gg.s), _ptr(ob),
+                                         n_obs, float(kappa), float(dt), int(n_particles), int(seed),
+                                         int(max_steps), _ptr(out["mean"]), _ptr(out["var"]),
+                                         _ptr(out["tau_mean"]), _ptr(out["tau_var"]), _ptr(out["n_capped"]),
+                                         _ptr(pt))
+        _check(st, "pm_observe_dirichlet")
+        if paths:
+            out["paths"] = pt
+        return out
+
+    # -- replay / inspection ---------------------------------------------------------
+    def step(self, u, X, n, i, j, kappa, dt, seed):
+        torch = _torch()
+        self.ctx.bind_stream()
+        dev = self.ctx.device
+        Xt = _dev(X, torch.float64, dev).reshape(-1, 2)
+        cnt = Xt.shape[0]
+        nt = _dev(np.broadcast_to(np.asarray(n, dtype=np.int64), (cnt,)), torch.int64, dev)
+        it = _dev(np.broadcast_to(np.asarray(i, dtype=np.int64), (cnt,)).astype(np.int32), torch.int32, dev)
+        jt = _dev(np.broadcast_to(np.asarray(j, dtype=np.int64), (cnt,)).astype(np.int32), torch.int32, dev)
+        Y = torch.empty_like(Xt)
+        st = _lib().pm_step(self.ctx.h, self.h, _ptr(self._u(u)), cnt, _ptr(Xt), _ptr(nt), _ptr(it), _ptr(jt),
+                            float(kappa), float(dt), int(seed), _ptr(Y))
+        _check(st, "pm_step")
+        return Y
+
+    def velocity(self, u, X):
+        torch = _torch()
+        self.ctx.bind_stream()
+        Xt = _dev(X, torch.float64, self.ctx.device).reshape(-1, 2)
+        V = torch.empty_like(Xt)
+        st = _lib().pm_velocity(self.ctx.h, self.h, _ptr(self._u(u)), Xt.shape[0], _ptr(Xt), _ptr(V))
+        _check(st, "pm_velocity")
+        return V
+
+    def normals(self, n, i, j, seed):
+        torch = _torch()
+        self.ctx.bind_stream()
+        dev = self.ctx.device
+        n = np.atleast_1d(np.asarray(n, dtype=np.int64))
+        cnt = n.size
+        nt = _dev(n, torch.int64, dev)
+        it = _dev(np.broadcast_to(np.asarray(i, dtype=np.int64), (cnt,)).astype(np.int32), torch.int32, dev)
+        jt = _dev(np.broadcast_to(np.asarray(j, dtype=np.int64), (cnt,)).astype(np.int32), torch.int32, dev)
+        Z = torch.empty((cnt, 2), dtype=torch.float64, device=dev)
+        st = _lib().pm_normals(self.ctx.h, self.h, cnt, _ptr(nt), _ptr(it), _ptr(jt), int(seed), _ptr(Z))
+        _check(st, "pm_normals")
+        return Z
+
+
+def n_steps(T: float, dt: float) -> int:
+    """Number of uniform steps the library takes to reach T: ceil(T/dt) (to 1e-9)."""
+    import math
+    return int(math.ceil(T / dt - 1e-9))

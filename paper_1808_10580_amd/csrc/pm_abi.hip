@@ -1,0 +1,659 @@
+// pm_abi.hip -- the extern "C" boundary of libpm.so (declared in include/pm.h).
+//
+// Host-side validation, workspace management and launch sequencing.  All
+// arithmetic of the method runs in the kernels of pm_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pm_kernels.h"
+
+using namespace pm;
+
+struct pm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n_cu = 1;
+    unsigned *d_flags = nullptr;
+    unsigned long long *d_queue = nullptr;
+    void *coef = nullptr;
+    size_t coef_cap = 0;
+    void *part = nullptr;
+    size_t part_cap = 0;
+    void *part2 = nullptr;
+    size_t part2_cap = 0;
+    void *pay = nullptr;
+    size_t pay_cap = 0;
+    void *tau = nullptr;
+    size_t tau_cap = 0;
+    void *capped = nullptr;
+    size_t capped_cap = 0;
+    void *states = nullptr;
+    size_t states_cap = 0;
+    void *exitp = nullptr;
+    size_t exitp_cap = 0;
+    void *integ = nullptr;
+    size_t integ_cap = 0;
+    void *meta = nullptr;
+    size_t meta_cap = 0;
+    int64_t *h_meta = nullptr;  // pinned staging for batch metadata
+    size_t h_meta_cap = 0;
+    hipEvent_t meta_ev = nullptr;
+    bool meta_pending = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    double last_steps = 0.0;
+    int ppl = 0;  // 0 = default
+    int src = 0;
+};
+
+struct pm_problem {
+    pm_ctx *ctx = nullptr;
+    int domain = PM_TORUS;
+    int prec = PM_FP32;
+    int n_modes = 0;
+    int K = 0;
+    int32_t *d_k = nullptr;
+    double v0[2] = {0.0, 0.0};
+    bool has_theta0 = false;
+    FieldArg theta0{};
+};
+
+namespace {
+
+#define PM_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return PM_EDEVICE;       \
+    } while (0)
+
+int ensure(pm_ctx *c, void **ptr, size_t *cap, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    if (*cap >= bytes) return PM_OK;
+    if (*ptr) {
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return PM_EDEVICE;
+        (void)hipFree(*ptr);
+        *ptr = nullptr;
+        *cap = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    if (hipMalloc(ptr, want) != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return PM_ENOMEM;
+    }
+    *cap = want;
+    return PM_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int to_field(const pm_field *f, FieldArg *out)
+{
+    if (!f) return PM_EINVAL;
+    if (f->kind < PM_F_ZERO || f->kind > PM_F_LINEAR) return PM_EINVAL;
+    if (f->n_params < 0 || f->n_params > PM_FIELD_MAX_PARAMS) return PM_EINVAL;
+    if (f->n_params > 0 && !f->params) return PM_EINVAL;
+    static const int need[] = {0, 1, 1, 4, 4, 1, 2, 3};
+    const int n = f->n_params;
+    if (n < need[f->kind]) return PM_EINVAL;
+    if ((f->kind == PM_F_FOURIER || f->kind == PM_F_GAUSS_PERIODIC) && (n % 4) != 0) return PM_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    out->kind = f->kind;
+    out->n = n;
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(f->params[i])) return PM_EINVAL;
+        out->p[i] = f->params[i];
+    }
+    if (f->kind == PM_F_GAUSS_PERIODIC)
+        for (int m = 0; m < n; m += 4)
+            if (!(out->p[m + 2] > 0.0)) return PM_EINVAL;
+    return PM_OK;
+}
+
+int64_t n_steps_of(double T, double dt) { return (int64_t)std::ceil(T / dt - 1e-9); }
+
+template <typename T>
+int fold(pm_ctx *c, const pm_problem *p, const double *u, int n_sets, int64_t u_stride, T **coef_out,
+         int64_t *stride_out)
+{
+    const int B = 2 * p->K + 1;
+    const int R = row_stride(p->domain, p->K);
+    const int64_t stride = (int64_t)B * R;
+    int st = ensure(c, &c->coef, &c->coef_cap, (size_t)n_sets * stride * sizeof(T));
+    if (st) return st;
+    FoldArgs fa{};
+    fa.k = p->d_k;
+    fa.n_modes = p->n_modes;
+    fa.K = p->K;
+    fa.domain = p->domain;
+    fa.row_stride = R;
+    fa.u = u;
+    fa.u_stride = u_stride;
+    fa.coef_stride = stride;
+    if (launch_fold<T>(fa, (T *)c->coef, n_sets, c->stream) != hipSuccess) return PM_EDEVICE;
+    *coef_out = (T *)c->coef;
+    *stride_out = stride;
+    return PM_OK;
+}
+
+int default_ppl(const pm_ctx *c) { return c->ppl ? c->ppl : 2; }
+
+template <typename T>
+int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, const int64_t *nps,
+                      const uint64_t *seeds, const double *obs, int n_obs, double kappa, double T_,
+                      double dt, double *mean, double *var, double *endpoints)
+{
+    const int64_t Nt = n_steps_of(T_, dt);
+    const double dte = T_ / (double)Nt;
+    T *coef;
+    int64_t cstride;
+    int st = fold<T>(c, p, u, n_u, 2 * (int64_t)p->n_modes, &coef, &cstride);
+    if (st) return st;
+
+    const int ppl = std::is_same<T, double>::value ? 1 : default_ppl(c);
+    TimeArgs<T> a{};
+    a.coef = coef;
+    a.coef_stride = cstride;
+    a.obs = obs;
+    a.n_obs = n_obs;
+    a.n_u = n_u;
+    a.n_steps = Nt;
+    a.dt = (T)dte;
+    a.sq = (T)std::sqrt(2.0 * kappa * dte);
+    a.v0x = (T)p->v0[0];
+    a.v0y = (T)p->v0[1];
+    a.queue = c->d_queue;
+
+    PayArgs<T> pa{};
+    pa.n_u = n_u;
+    pa.theta0 = p->theta0;
+    pa.endpoints = endpoints;
+    pa.flags = c->d_flags;
+
+    FinalArgs fa{};
+    fa.n_obs = n_obs;
+    fa.mean = mean;
+    fa.var = var;
+    fa.flags = c->d_flags;
+
+    int64_t total_chunks;
+    double steps = 0.0;
+    if (n_u == 1) {
+        const int64_t cpo = (nps[0] + 63) / 64;
+        total_chunks = cpo * n_obs;
+        a.np0 = nps[0];
+        a.seed0 = seeds[0];
+        a.n_tasks = (total_chunks + ppl - 1) / ppl;
+        pa.np0 = nps[0];
+        fa.cpo = cpo;
+        steps = (double)nps[0] * n_obs * (double)Nt;
+    } else {
+        // metadata: np[n_u] seed[n_u] task_off[n_u+1] chunk_off[n_u+1]
+        const size_t nmeta = (size_t)4 * n_u + 2;
+        if (c->meta_pending) {
+            if (hipEventSynchronize(c->meta_ev) != hipSuccess) return PM_EDEVICE;
+            c->meta_pending = false;
+        }
+        if (c->h_meta_cap < nmeta) {
+            if (c->h_meta) (void)hipHostFree(c->h_meta);
+            c->h_meta = nullptr;
+            c->h_meta_cap = 0;
+            if (hipHostMalloc((void **)&c->h_meta, nmeta * sizeof(int64_t)) != hipSuccess) return PM_ENOMEM;
+            c->h_meta_cap = nmeta;
+        }
+        st = ensure(c, &c->meta, &c->meta_cap, nmeta * sizeof(int64_t));
+        if (st) return st;
+        int64_t *h = c->h_meta;
+        int64_t *h_np = h, *h_tk = h + 2 * n_u, *h_ch = h + 3 * n_u + 1;
+        uint64_t *h_sd = (uint64_t *)(h + n_u);
+        h_tk[0] = 0;
+        h_ch[0] = 0;
+        for (int b = 0; b < n_u; ++b) {
+            const int64_t cpo = (nps[b] + 63) / 64;
+            const int64_t nch = cpo * n_obs;
+            h_np[b] = nps[b];
+            h_sd[b] = seeds[b];
+            h_ch[b + 1] = h_ch[b] + nch;
+            h_tk[b + 1] = h_tk[b] + (nch + ppl - 1) / ppl;
+            steps += (double)nps[b] * n_obs * (double)Nt;
+        }
+        PM_HIP(hipMemcpyAsync(c->meta, h, nmeta * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+        PM_HIP(hipEventRecord(c->meta_ev, c->stream));
+        c->meta_pending = true;
+        const int64_t *d = (const int64_t *)c->meta;
+        a.np_arr = d;
+        a.seed_arr = (const uint64_t *)(d + n_u);
+        a.task_off = d + 2 * n_u;
+        a.chunk_off = d + 3 * n_u + 1;
+        a.n_tasks = h_tk[n_u];
+        total_chunks = h_ch[n_u];
+        fa.chunk_off = a.chunk_off;
+        fa.np_arr = a.np_arr;
+        pa.chunk_off = a.chunk_off;
+        pa.np_arr = a.np_arr;
+    }
+    st = ensure(c, &c->part, &c->part_cap, (size_t)total_chunks * 3 * sizeof(double));
+    if (st) return st;
+    st = ensure(c, &c->states, &c->states_cap, (size_t)total_chunks * 64 * 2 * sizeof(T));
+    if (st) return st;
+    a.states = (T *)c->states;
+    pa.states = a.states;
+    pa.n_chunks = total_chunks;
+    pa.partials = (double *)c->part;
+    fa.partials = pa.partials;
+
+    if (launch_zero_u64(c->d_queue, 1, c->stream) != hipSuccess) return PM_EDEVICE;
+    PM_HIP(hipEventRecord(c->ev0, c->stream));
+    if (launch_time<T>(a, p->K, ppl, c->src, c->n_cu, c->stream) != hipSuccess) return PM_EDEVICE;
+    PM_HIP(hipEventRecord(c->ev1, c->stream));
+    c->timed = true;
+    c->last_steps = steps;
+    if (launch_time_payoff<T>(pa, c->stream) != hipSuccess) return PM_EDEVICE;
+    if (launch_finalize(fa, n_u * n_obs, c->stream) != hipSuccess) return PM_EDEVICE;
+    return PM_OK;
+}
+
+template <typename T>
+int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, const FieldArg &f,
+                           const FieldArg &g, const double *obs, int n_obs, double kappa, double dt,
+                           int64_t np, uint64_t seed, int64_t max_steps, double *mean, double *var,
+                           double *tau_mean, double *tau_var, int64_t *n_capped, double *paths)
+{
+    T *coef;
+    int64_t cstride;
+    int st = fold<T>(c, p, u, 1, 2 * (int64_t)p->n_modes, &coef, &cstride);
+    if (st) return st;
+    const int64_t total = np * n_obs;
+    if ((st = ensure(c, &c->pay, &c->pay_cap, total * sizeof(double)))) return st;
+    if ((st = ensure(c, &c->tau, &c->tau_cap, total * sizeof(double)))) return st;
+    if ((st = ensure(c, &c->integ, &c->integ_cap, total * sizeof(double)))) return st;
+    if ((st = ensure(c, &c->exitp, &c->exitp_cap, 2 * total * sizeof(double)))) return st;
+    if ((st = ensure(c, &c->capped, &c->capped_cap, total))) return st;
+    const int64_t cpo = (np + 63) / 64;
+    if ((st = ensure(c, &c->part, &c->part_cap, cpo * n_obs * 3 * sizeof(double)))) return st;
+    if ((st = ensure(c, &c->part2, &c->part2_cap, cpo * n_obs * 3 * sizeof(double)))) return st;
+
+    // zero, constant and linear sources run as f = p0 x + p1 y + p2 in the walk
+    int fk = 1;
+    FieldArg fpoly{};
+    if (f.kind == PM_F_ZERO || f.kind == PM_F_CONST || f.kind == PM_F_LINEAR) {
+        fk = 0;
+        fpoly.kind = PM_F_LINEAR;
+        fpoly.n = 3;
+        if (f.kind == PM_F_CONST) fpoly.p[2] = f.p[0];
+        if (f.kind == PM_F_LINEAR) {
+            fpoly.p[0] = f.p[0];
+            fpoly.p[1] = f.p[1];
+            fpoly.p[2] = f.p[2];
+        }
+    }
+
+    DirArgs<T> a{};
+    a.coef = coef;
+    a.obs = obs;
+    a.n_obs = n_obs;
+    a.np = np;
+    a.total = total;
+    a.seed = seed;
+    a.max_steps = max_steps;
+    a.dt = (T)dt;
+    a.dtd = dt;
+    a.sq = (T)std::sqrt(2.0 * kappa * dt);
+    a.v0x = (T)p->v0[0];
+    a.v0y = (T)p->v0[1];
+    a.f = fk == 0 ? fpoly : f;
+    a.exitp = (double *)c->exitp;
+    a.integ = (double *)c->integ;
+    a.tau = (double *)c->tau;
+    a.capped = (unsigned char *)c->capped;
+    a.queue = c->d_queue;
+
+    if (launch_zero_u64(c->d_queue, 1, c->stream) != hipSuccess) return PM_EDEVICE;
+    PM_HIP(hipEventRecord(c->ev0, c->stream));
+    if (launch_dirichlet<T>(a, p->K, fk, c->n_cu, c->stream) != hipSuccess) return PM_EDEVICE;
+    PM_HIP(hipEventRecord(c->ev1, c->stream));
+    c->timed = true;
+    c->last_steps = -1.0;  // counted by the caller from the exit steps
+
+    DirPayArgs pa{};
+    pa.total = total;
+    pa.dtd = dt;
+    pa.g = g;
+    pa.exitp = a.exitp;
+    pa.integ = a.integ;
+    pa.tau = a.tau;
+    pa.capped = a.capped;
+    pa.pay = (double *)c->pay;
+    pa.paths = paths;
+    pa.flags = c->d_flags;
+    if (launch_dir_payoff(pa, c->stream) != hipSuccess) return PM_EDEVICE;
+    if (launch_chunk_reduce(pa.pay, np, n_obs, (double *)c->part, c->d_flags, c->stream)) return PM_EDEVICE;
+    if (launch_chunk_reduce(a.tau, np, n_obs, (double *)c->part2, c->d_flags, c->stream)) return PM_EDEVICE;
+    FinalArgs fa{};
+    fa.n_obs = n_obs;
+    fa.cpo = cpo;
+    fa.flags = c->d_flags;
+    fa.partials = (const double *)c->part;
+    fa.mean = mean;
+    fa.var = var;
+    if (launch_finalize(fa, n_obs, c->stream) != hipSuccess) return PM_EDEVICE;
+    fa.partials = (const double *)c->part2;
+    fa.mean = tau_mean;
+    fa.var = tau_var;
+    if (launch_finalize(fa, n_obs, c->stream) != hipSuccess) return PM_EDEVICE;
+    if (launch_count_capped(a.capped, np, n_obs, n_capped, c->stream) != hipSuccess) return PM_EDEVICE;
+    return PM_OK;
+}
+
+bool bad_ptr(const void *p) { return p == nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+const char *pm_strerror(int s)
+{
+    switch (s) {
+    case PM_OK: return "ok";
+    case PM_EINVAL: return "invalid argument";
+    case PM_ENOMEM: return "device allocation failed";
+    case PM_EDEVICE: return "HIP runtime error";
+    case PM_ENONFINITE: return "non-finite payoff or statistic";
+    case PM_ECAPPED: return "a Dirichlet path reached max_steps";
+    case PM_EUNSUPPORTED: return "outside the compiled kernel set";
+    default: return "unknown status";
+    }
+}
+
+int pm_create(pm_ctx **out, int device, void *stream)
+{
+    if (!out) return PM_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return PM_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return PM_EDEVICE;
+    pm_ctx *c = new (std::nothrow) pm_ctx();
+    if (!c) return PM_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return PM_EDEVICE;
+    }
+    c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    if (hipMalloc((void **)&c->d_flags, 64) != hipSuccess ||
+        hipMalloc((void **)&c->d_queue, 64) != hipSuccess ||
+        hipMemset(c->d_flags, 0, 64) != hipSuccess ||
+        hipMemset(c->d_queue, 0, 64) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipEventCreateWithFlags(&c->meta_ev, hipEventDisableTiming) != hipSuccess) {
+        pm_destroy(c);
+        return PM_EDEVICE;
+    }
+    *out = c;
+    return PM_OK;
+}
+
+void pm_destroy(pm_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    void *bufs[] = {c->d_flags, c->d_queue, c->coef, c->part, c->part2, c->pay, c->tau, c->capped,
+                    c->meta, c->states, c->exitp, c->integ};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    if (c->h_meta) (void)hipHostFree(c->h_meta);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->meta_ev) (void)hipEventDestroy(c->meta_ev);
+    delete c;
+}
+
+int pm_set_stream(pm_ctx *c, void *stream)
+{
+    if (!c) return PM_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return PM_OK;
+}
+
+int pm_set_tuning(pm_ctx *c, int ppl, int src)
+{
+    if (!c) return PM_EINVAL;
+    if (!(ppl == 0 || ppl == 1 || ppl == 2 || ppl == 4)) return PM_EINVAL;
+    if (!(src == 0 || src == 1)) return PM_EINVAL;
+    c->ppl = ppl;
+    c->src = src;
+    return PM_OK;
+}
+
+int pm_problem_create(pm_ctx *c, pm_problem **out, int domain, int n_modes, const int32_t *k,
+                      const double *v0, const pm_field *theta0, int prec)
+{
+    if (!c || !out) return PM_EINVAL;
+    *out = nullptr;
+    if (domain != PM_TORUS && domain != PM_DISK) return PM_EINVAL;
+    if (prec != PM_FP32 && prec != PM_FP64) return PM_EINVAL;
+    if (n_modes < 0 || (n_modes > 0 && !k)) return PM_EINVAL;
+    int K = 0;
+    for (int m = 0; m < n_modes; ++m) {
+        const int ax = k[2 * m] < 0 ? -k[2 * m] : k[2 * m];
+        const int ay = k[2 * m + 1] < 0 ? -k[2 * m + 1] : k[2 * m + 1];
+        if (ax > PM_MAX_K || ay > PM_MAX_K) return PM_EUNSUPPORTED;
+        if (ax > K) K = ax;
+        if (ay > K) K = ay;
+    }
+    if (v0 && (!std::isfinite(v0[0]) || !std::isfinite(v0[1]))) return PM_EINVAL;
+    FieldArg th{};
+    if (theta0) {
+        if (domain != PM_TORUS) return PM_EINVAL;
+        if (to_field(theta0, &th) != PM_OK) return PM_EINVAL;
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    pm_problem *p = new (std::nothrow) pm_problem();
+    if (!p) return PM_ENOMEM;
+    p->ctx = c;
+    p->domain = domain;
+    p->prec = prec;
+    p->n_modes = n_modes;
+    p->K = K;
+    if (v0) {
+        p->v0[0] = v0[0];
+        p->v0[1] = v0[1];
+    }
+    p->has_theta0 = theta0 != nullptr;
+    p->theta0 = th;
+    const size_t kb = (size_t)(n_modes > 0 ? n_modes : 1) * 2 * sizeof(int32_t);
+    if (hipMalloc((void **)&p->d_k, kb) != hipSuccess) {
+        delete p;
+        return PM_ENOMEM;
+    }
+    if (n_modes > 0 &&
+        hipMemcpy(p->d_k, k, (size_t)n_modes * 2 * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(p->d_k);
+        delete p;
+        return PM_EDEVICE;
+    }
+    *out = p;
+    return PM_OK;
+}
+
+void pm_problem_destroy(pm_problem *p)
+{
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipStreamSynchronize(p->ctx->stream);
+    if (p->d_k) (void)hipFree(p->d_k);
+    delete p;
+}
+
+static int check_time_args(double kappa, double T, double dt)
+{
+    if (!(std::isfinite(kappa) && kappa >= 0.0)) return PM_EINVAL;
+    if (!finite_pos(T) || !finite_pos(dt)) return PM_EINVAL;
+    const int64_t Nt = n_steps_of(T, dt);
+    if (Nt < 1 || Nt > ((int64_t)1 << 33)) return PM_EINVAL;
+    return PM_OK;
+}
+
+int pm_observe_time(pm_ctx *c, const pm_problem *p, const double *u, const double *obs, int n_obs,
+                    double kappa, double T, double dt, int64_t np, uint64_t seed, double *mean,
+                    double *var, double *endpoints)
+{
+    if (!c || !p || p->ctx != c) return PM_EINVAL;
+    if (p->domain != PM_TORUS || !p->has_theta0) return PM_EINVAL;
+    if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(obs) || bad_ptr(mean) || bad_ptr(var)) return PM_EINVAL;
+    if (n_obs < 1) return PM_EINVAL;
+    if (np < 1 || np > ((int64_t)1 << 32)) return PM_EINVAL;
+    if (check_time_args(kappa, T, dt)) return PM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    if (p->prec == PM_FP64)
+        return observe_time_impl<double>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, T, dt, mean, var, endpoints);
+    return observe_time_impl<float>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, T, dt, mean, var, endpoints);
+}
+
+int pm_observe_time_batch(pm_ctx *c, const pm_problem *p, int n_u, const double *u,
+                          const int64_t *nps, const uint64_t *seeds, const double *obs, int n_obs,
+                          double kappa, double T, double dt, double *mean, double *var)
+{
+    if (!c || !p || p->ctx != c) return PM_EINVAL;
+    if (p->domain != PM_TORUS || !p->has_theta0) return PM_EINVAL;
+    if (n_u < 1 || !nps || !seeds) return PM_EINVAL;
+    if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(obs) || bad_ptr(mean) || bad_ptr(var)) return PM_EINVAL;
+    if (n_obs < 1) return PM_EINVAL;
+    for (int b = 0; b < n_u; ++b)
+        if (nps[b] < 1 || nps[b] > ((int64_t)1 << 32)) return PM_EINVAL;
+    if (check_time_args(kappa, T, dt)) return PM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    if (p->prec == PM_FP64)
+        return observe_time_impl<double>(c, p, n_u, u, nps, seeds, obs, n_obs, kappa, T, dt, mean, var, nullptr);
+    return observe_time_impl<float>(c, p, n_u, u, nps, seeds, obs, n_obs, kappa, T, dt, mean, var, nullptr);
+}
+
+int pm_observe_dirichlet(pm_ctx *c, const pm_problem *p, const double *u, const pm_field *f,
+                         const pm_field *g, const double *obs, int n_obs, double kappa, double dt,
+                         int64_t np, uint64_t seed, int64_t max_steps, double *mean, double *var,
+                         double *tau_mean, double *tau_var, int64_t *n_capped, double *paths)
+{
+    if (!c || !p || p->ctx != c) return PM_EINVAL;
+    if (p->domain != PM_DISK) return PM_EINVAL;
+    if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(obs) || bad_ptr(mean) || bad_ptr(var) ||
+        bad_ptr(tau_mean) || bad_ptr(tau_var) || bad_ptr(n_capped))
+        return PM_EINVAL;
+    FieldArg ff, gg;
+    if (to_field(f, &ff) != PM_OK || to_field(g, &gg) != PM_OK) return PM_EINVAL;
+    if (n_obs < 1) return PM_EINVAL;
+    if (np < 1 || np > ((int64_t)1 << 32)) return PM_EINVAL;
+    if (!(std::isfinite(kappa) && kappa > 0.0) || !finite_pos(dt)) return PM_EINVAL;
+    if (max_steps < 1 || max_steps > ((int64_t)1 << 33)) return PM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    if (p->prec == PM_FP64)
+        return observe_dirichlet_impl<double>(c, p, u, ff, gg, obs, n_obs, kappa, dt, np, seed, max_steps,
+                                              mean, var, tau_mean, tau_var, n_capped, paths);
+    return observe_dirichlet_impl<float>(c, p, u, ff, gg, obs, n_obs, kappa, dt, np, seed, max_steps, mean,
+                                         var, tau_mean, tau_var, n_capped, paths);
+}
+
+int pm_step(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, const double *X,
+            const uint64_t *n, const uint32_t *i, const uint32_t *j, double kappa, double dt,
+            uint64_t seed, double *Y)
+{
+    if (!c || !p || p->ctx != c) return PM_EINVAL;
+    if (count < 0) return PM_EINVAL;
+    if (count == 0) return PM_OK;
+    if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(X) || bad_ptr(n) || bad_ptr(i) || bad_ptr(j) || bad_ptr(Y))
+        return PM_EINVAL;
+    if (!(std::isfinite(kappa) && kappa >= 0.0) || !finite_pos(dt)) return PM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    auto run = [&](auto tag) -> int {
+        using T = decltype(tag);
+        T *coef;
+        int64_t cs;
+        int st = fold<T>(c, p, u, 1, 2 * (int64_t)p->n_modes, &coef, &cs);
+        if (st) return st;
+        StepArgs<T> a{};
+        a.coef = coef;
+        a.domain = p->domain;
+        a.count = count;
+        a.X = X;
+        a.n = n;
+        a.i = i;
+        a.j = j;
+        a.seed = seed;
+        a.dt = (T)dt;
+        a.sq = (T)std::sqrt(2.0 * kappa * dt);
+        a.v0x = (T)p->v0[0];
+        a.v0y = (T)p->v0[1];
+        a.Y = Y;
+        return launch_step<T>(a, p->K, c->stream) == hipSuccess ? PM_OK : PM_EDEVICE;
+    };
+    return p->prec == PM_FP64 ? run(double{}) : run(float{});
+}
+
+int pm_velocity(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, const double *X, double *V)
+{
+    if (!c || !p || p->ctx != c) return PM_EINVAL;
+    if (count < 0) return PM_EINVAL;
+    if (count == 0) return PM_OK;
+    if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(X) || bad_ptr(V)) return PM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    auto run = [&](auto tag) -> int {
+        using T = decltype(tag);
+        T *coef;
+        int64_t cs;
+        int st = fold<T>(c, p, u, 1, 2 * (int64_t)p->n_modes, &coef, &cs);
+        if (st) return st;
+        return launch_velocity<T>(coef, p->domain, p->K, (T)p->v0[0], (T)p->v0[1], count, X, V, c->stream) ==
+                       hipSuccess
+                   ? PM_OK
+                   : PM_EDEVICE;
+    };
+    return p->prec == PM_FP64 ? run(double{}) : run(float{});
+}
+
+int pm_normals(pm_ctx *c, const pm_problem *p, int64_t count, const uint64_t *n, const uint32_t *i,
+               const uint32_t *j, uint64_t seed, double *Z)
+{
+    if (!c || !p || p->ctx != c) return PM_EINVAL;
+    if (count < 0) return PM_EINVAL;
+    if (count == 0) return PM_OK;
+    if (bad_ptr(n) || bad_ptr(i) || bad_ptr(j) || bad_ptr(Z)) return PM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    hipError_t e = p->prec == PM_FP64 ? launch_normals<double>(count, n, i, j, seed, Z, c->stream)
+                                      : launch_normals<float>(count, n, i, j, seed, Z, c->stream);
+    return e == hipSuccess ? PM_OK : PM_EDEVICE;
+}
+
+int pm_sync(pm_ctx *c)
+{
+    if (!c) return PM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return PM_EDEVICE;
+    if (hipGetLastError() != hipSuccess) return PM_EDEVICE;
+    unsigned h = 0;
+    if (hipMemcpy(&h, c->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess) return PM_EDEVICE;
+    if (h && hipMemset(c->d_flags, 0, sizeof(unsigned)) != hipSuccess) return PM_EDEVICE;
+    if (h & PM_FLAG_NONFINITE) return PM_ENONFINITE;
+    if (h & PM_FLAG_CAPPED) return PM_ECAPPED;
+    return PM_OK;
+}
+
+int pm_last_kernel_stats(pm_ctx *c, double *ms, double *steps)
+{
+    if (!c || !ms || !steps) return PM_EINVAL;
+    if (!c->timed) return PM_EINVAL;
+    float f = 0.f;
+    if (hipEventElapsedTime(&f, c->ev0, c->ev1) != hipSuccess) return PM_EDEVICE;
+    *ms = f;
+    *steps = c->last_steps;
+    return PM_OK;
+}
+
+}  // extern "C"

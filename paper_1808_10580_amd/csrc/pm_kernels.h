@@ -1,0 +1,145 @@
+// pm_kernels.h -- kernel argument blocks and launchers shared by the kernels
+// (pm_kernels.hip) and the C ABI (pm_abi.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "pm_device.h"
+
+namespace pm {
+
+enum : unsigned { PM_FLAG_NONFINITE = 1u, PM_FLAG_CAPPED = 2u };
+enum { PM_COEF_LDS = 0, PM_COEF_SCALAR = 1 };
+
+struct FoldArgs {
+    const int32_t *k;  // device [M][2]
+    int n_modes;
+    int K;
+    int domain;
+    int row_stride;
+    const double *u;  // device [n_sets][u_stride]
+    int64_t u_stride;
+    int64_t coef_stride;  // elements between parameter sets in the output
+};
+
+template <typename T>
+struct TimeArgs {
+    const T *coef;
+    int64_t coef_stride;
+    const double *obs;
+    int n_obs;
+    int n_u;
+    int64_t np0;     // n_u == 1
+    uint64_t seed0;  // n_u == 1
+    const int64_t *np_arr;     // n_u > 1: device [n_u]
+    const uint64_t *seed_arr;  // device [n_u]
+    const int64_t *task_off;   // device [n_u+1]
+    const int64_t *chunk_off;  // device [n_u+1]
+    int64_t n_tasks;
+    int64_t n_steps;
+    T dt, sq, v0x, v0y;
+    T *states;  // [total chunks][64][2] final positions
+    unsigned long long *queue;
+};
+
+template <typename T>
+struct PayArgs {
+    const T *states;
+    int64_t n_chunks;
+    int n_u;
+    int64_t np0;
+    const int64_t *np_arr;
+    const int64_t *chunk_off;
+    FieldArg theta0;
+    double *partials;
+    double *endpoints;  // nullable (n_u == 1)
+    unsigned *flags;
+};
+
+template <typename T>
+struct DirArgs {
+    const T *coef;
+    const double *obs;
+    int n_obs;
+    int64_t np;
+    int64_t total;
+    uint64_t seed;
+    int64_t max_steps;
+    T dt, sq, v0x, v0y;
+    double dtd;
+    FieldArg f;
+    double *exitp;  // [total][2]
+    double *integ;  // [total] int_0^tau f dt
+    double *tau;    // [total] exit time
+    unsigned char *capped;
+    unsigned long long *queue;
+};
+
+struct DirPayArgs {
+    int64_t total;
+    double dtd;
+    FieldArg g;
+    const double *exitp;
+    const double *integ;
+    const double *tau;
+    const unsigned char *capped;
+    double *pay;
+    double *paths;  // nullable
+    unsigned *flags;
+};
+
+struct FinalArgs {
+    const double *partials;
+    int n_obs;
+    int64_t cpo;                // single parameter set
+    const int64_t *chunk_off;   // batches: device [n_u+1], else nullptr
+    const int64_t *np_arr;      // batches: device [n_u]
+    double *mean;
+    double *var;
+    unsigned *flags;
+};
+
+template <typename T>
+struct StepArgs {
+    const T *coef;
+    int domain;
+    int64_t count;
+    const double *X;
+    const uint64_t *n;
+    const uint32_t *i;
+    const uint32_t *j;
+    uint64_t seed;
+    T dt, sq, v0x, v0y;
+    double *Y;
+};
+
+int row_stride(int domain, int K);
+
+template <typename T>
+hipError_t launch_fold(const FoldArgs &a, T *coef, int n_sets, hipStream_t st);
+template <typename T>
+hipError_t launch_time(const TimeArgs<T> &a, int K, int ppl, int src, int n_cu, hipStream_t st);
+template <typename T>
+hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int n_cu, hipStream_t st);
+hipError_t launch_dir_payoff(const DirPayArgs &a, hipStream_t st);
+template <typename T>
+hipError_t launch_time_payoff(const PayArgs<T> &a, hipStream_t st);
+hipError_t launch_chunk_reduce(const double *vals, int64_t np, int n_obs, double *partials,
+                               unsigned *flags, hipStream_t st);
+hipError_t launch_finalize(const FinalArgs &a, int n_groups, hipStream_t st);
+hipError_t launch_count_capped(const unsigned char *capped, int64_t np, int n_obs, int64_t *out,
+                               hipStream_t st);
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
+template <typename T>
+hipError_t launch_step(const StepArgs<T> &a, int K, hipStream_t st);
+template <typename T>
+hipError_t launch_velocity(const T *coef, int domain, int K, T v0x, T v0y, int64_t count,
+                           const double *X, double *V, hipStream_t st);
+template <typename T>
+hipError_t launch_normals(int64_t count, const uint64_t *n, const uint32_t *i, const uint32_t *j,
+                          uint64_t seed, double *Z, hipStream_t st);
+
+}  // namespace pm

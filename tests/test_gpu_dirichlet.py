@@ -1,0 +1,140 @@
+"""GPU parity of Algorithm 2 (Dirichlet problem on the unit disk) against the oracle.
+
+  - teacher-forced single steps from oracle states (no wrap on the disk);
+  - FP64 paths: every exit step equal (an integer decided by the FP64 test
+    |Y|^2 >= 1 on both sides), exit points, payoffs and means to 1e-12;
+  - FP32 paths: the fraction of paths whose exit step differs is small, and
+    the observation means agree with the oracle's by a paired 4-SE test;
+  - capped paths are counted and reported by pm_sync;
+  - the full-size disk workload against an oracle subsample.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+OBS = np.array([[0.0, 0.0], [0.3, 0.1], [-0.2, 0.5], [0.6, -0.3], [0.1, -0.75]])
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1808_10580_amd as pm
+    pm.lib()
+    return pm
+
+
+@pytest.fixture(scope="module")
+def ctx(pm):
+    return pm.Context(0)
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def _flow():
+    wl = W.dirichlet_main()
+    return wl.modes, wl.u
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-6)])
+def test_teacher_forced_disk_steps(pm, ctx, orc, prec, tol):
+    modes, u = _flow()
+    kappa, dt = 0.02, 1e-4
+    rows = []
+    for j in range(len(OBS)):
+        for i in range(8):
+            P = orc.path("disk", modes, u, kappa, dt, 3, i, j, OBS[j], 300)
+            r2 = (P ** 2).sum(1)
+            last = np.argmax(r2 >= 1) if np.any(r2 >= 1) else 300
+            for n in range(0, max(last - 1, 1), 5):
+                rows.append((P[n], P[n + 1], n, i, j))
+    X = np.array([r[0] for r in rows])
+    Yref = np.array([r[1] for r in rows])
+    prob = pm.Problem(ctx, "disk", modes, prec=prec)
+    Y = np_(prob.step(u, X, [r[2] for r in rows], [r[3] for r in rows], [r[4] for r in rows], kappa, dt, 3))
+    assert np.max(np.abs(Y - Yref)) <= tol
+
+
+def _run_both(pm, ctx, orc, prec, Np=400, kappa=0.25, dt=1e-3, f=None, g=None, seed=31, max_steps=10**6):
+    modes, u = _flow()
+    f = f or W.fld("const", [-1.0])
+    g = g or W.fld("cos_m_theta", [3])
+    prob = pm.Problem(ctx, "disk", modes, prec=prec)
+    out = prob.observe_dirichlet(u, f, g, OBS, kappa, dt, Np, seed, max_steps, paths=True)
+    st = ctx.sync()
+    ref = orc.observe_dirichlet_paths(modes, u, f, g, OBS, kappa, dt, Np, seed, max_steps)
+    return out, st, ref
+
+
+def test_fp64_dirichlet_paths_match_oracle(pm, ctx, orc):
+    out, st, ref = _run_both(pm, ctx, orc, "fp64")
+    assert st == pm.PM_OK
+    P = np_(out["paths"])
+    assert np.array_equal(P[..., 3].astype(np.int64), ref["tau_steps"])
+    assert np.max(np.abs(P[..., :2] - ref["exit"])) <= 1e-12
+    assert np.max(np.abs(P[..., 2] - ref["payoff"])) <= 1e-12 * max(1.0, np.max(np.abs(ref["payoff"])))
+    m, v = orc.mean_var(ref["payoff"])
+    assert np.max(np.abs(np_(out["mean"]) - m)) <= 1e-12 * max(1.0, np.max(np.abs(m)))
+    tm, tv = orc.mean_var(ref["tau_steps"] * 1e-3)
+    assert np.max(np.abs(np_(out["tau_mean"]) - tm)) <= 1e-12
+    assert np.all(np_(out["n_capped"]) == 0)
+
+
+def test_fp32_dirichlet_paths_and_means(pm, ctx, orc):
+    out, st, ref = _run_both(pm, ctx, orc, "fp32", Np=1000)
+    assert st == pm.PM_OK
+    P = np_(out["paths"])
+    same = P[..., 3].astype(np.int64) == ref["tau_steps"]
+    frac = 1 - same.mean()
+    print("fp32 Dirichlet: fraction of paths with a different exit step %.4f" % frac)
+    assert frac <= 0.02
+    assert np.max(np.abs(P[..., :2][same] - ref["exit"][same])) <= 1e-4
+    dd = P[..., 2] - ref["payoff"]
+    se = dd.std(axis=1, ddof=1) / math.sqrt(dd.shape[1]) + 1e-300
+    z = np.abs(np_(out["mean"]) - ref["payoff"].mean(axis=1)) / se
+    assert np.all(z < 4.5), z
+
+
+def test_linear_and_general_sources(pm, ctx, orc):
+    """f = linear runs inline in the walk; f = Gaussian bumps runs the general
+    field path.  Both match the oracle in FP64 path by path."""
+    for f in (W.fld("linear", [1.0, -0.5, 0.25]), W.fld("gauss_periodic", [0.2, 0.1, 0.3, 1.0])):
+        out, st, ref = _run_both(pm, ctx, orc, "fp64", Np=128, f=f, g=W.fld("exp_linear", [0.3, 0.1]))
+        P = np_(out["paths"])
+        assert np.array_equal(P[..., 3].astype(np.int64), ref["tau_steps"])
+        assert np.max(np.abs(P[..., 2] - ref["payoff"])) <= 1e-11
+
+
+def test_capped_paths_reported(pm, ctx, orc):
+    out, st, ref = _run_both(pm, ctx, orc, "fp64", Np=70, kappa=0.02, dt=1e-4, max_steps=11,
+                             f=W.fld("const", [1.0]), g=W.fld("const", [5.0]))
+    assert st == pm.PM_ECAPPED
+    assert np.all(np_(out["n_capped"]) == 70)
+    assert np.allclose(np_(out["mean"]), -11 * 1e-4, rtol=0, atol=1e-15)
+    assert ctx.sync() == pm.PM_OK  # flags are cleared
+
+
+def test_full_size_disk_workload_against_oracle_subsample(pm, ctx, orc):
+    """Disk workload at full size (25 x 5e4 particles, dt = 1e-4, walk to exit);
+    the oracle walks the first 24 particles of every point."""
+    wl = W.dirichlet_main()
+    prob = pm.Problem(ctx, "disk", wl.modes, prec="fp32")
+    out = prob.observe_dirichlet(wl.u, wl.f, wl.g, wl.obs, wl.kappa, wl.dt, wl.n_particles, wl.seed,
+                                 wl.max_steps)
+    assert ctx.sync() == pm.PM_OK
+    ref = orc.observe_dirichlet(wl.modes, wl.u, wl.f, wl.g, wl.obs, wl.kappa, wl.dt, 24, wl.seed,
+                                wl.max_steps)
+    se = np.sqrt(ref["var"] / 24 + np_(out["var"]) / wl.n_particles)
+    z = np.abs(np_(out["mean"]) - ref["mean"]) / se
+    assert np.sum(z > 3) <= 2 and np.all(z < 4.5), z
+    se_t = np.sqrt(ref["tau_var"] / 24 + np_(out["tau_var"]) / wl.n_particles)
+    zt = np.abs(np_(out["tau_mean"]) - ref["tau_mean"]) / se_t
+    assert np.sum(zt > 3) <= 2 and np.all(zt < 4.5), zt

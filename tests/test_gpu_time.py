@@ -1,0 +1,302 @@
+"""GPU parity of Algorithm 1 (time problem) against the FP64 oracle.
+
+Contract (the flow is chaotic at the main workload's horizon, so full-path
+agreement is checked where it is physically meaningful):
+  P0  building blocks: velocity and normals against the oracle at many points;
+  P1  teacher-forced single steps from oracle states: FP64 <= 1e-13,
+      FP32 <= 1e-6 (torus distance);
+  P2  FP64 full paths (small workload, 4 x 1000 x 100 steps): endpoints
+      <= 1e-12, and the observation means equal the oracle's to 1e-12;
+  P3  FP32 full paths where the oracle's twin-path amplification keeps the
+      bound: <= 1e-5 at the 99th percentile on the small workload, and on
+      the first 25 steps of the main workload; v = 0 paths over 1000 steps;
+  P4  observation means, FP32 against the oracle on the same Philox streams:
+      paired per-path differences, |mean d| <= 4 SE(d) per observation;
+  plus bitwise determinism across launch shapes, batching = separate calls,
+  ragged chunks, one particle, odd step counts and argument validation.
+Payoffs of both sides' endpoints for P4 are evaluated in the test with numpy,
+never by feeding GPU data into the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def tdist(a, b):
+    d = np.abs(np.asarray(a) - np.asarray(b))
+    d = np.mod(d, 1.0)
+    return np.minimum(d, 1.0 - d)
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1808_10580_amd as pm
+    pm.lib()
+    return pm
+
+
+@pytest.fixture(scope="module")
+def ctx(pm):
+    return pm.Context(0)
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def theta0_numpy(fd, X):
+    """Test-side evaluation of the initial conditions used here."""
+    x, y = X[..., 0], X[..., 1]
+    p = fd["params"]
+    if fd["kind"] == "sinsin":
+        return p[0] * np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y)
+    if fd["kind"] == "gauss_periodic":
+        out = np.zeros_like(x)
+        for m in range(0, len(p), 4):
+            cx, cy, s, A = p[m:m + 4]
+            for nx in (-1, 0, 1):
+                for ny in (-1, 0, 1):
+                    out += A * np.exp(-((x - cx - nx) ** 2 + (y - cy - ny) ** 2) / (2 * s * s))
+        return out
+    raise NotImplementedError(fd["kind"])
+
+
+# ---------------------------------------------------------------------------
+# P0: building blocks
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("K", [1, 2, 6, 8])
+def test_velocity_matches_oracle(pm, ctx, orc, prec, K):
+    rng = np.random.default_rng(K)
+    modes = W.torus_modes(K)
+    u = W.draw_prior(modes, rng)
+    X = rng.random((4096, 2))
+    prob = pm.Problem(ctx, "torus", modes, v0=(0.25, -0.5), theta0=W.fld("zero"), prec=prec)
+    V = np_(prob.velocity(u, X))
+    ref = orc.velocity("torus", modes, u, X, v0=(0.25, -0.5))
+    scale = np.max(np.abs(ref))
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert np.max(np.abs(V - ref)) <= tol * scale
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_disk_velocity_matches_oracle(pm, ctx, orc, prec):
+    rng = np.random.default_rng(3)
+    modes = W.disk_modes()
+    u = W.draw_prior(modes, rng)
+    X = W.uniform_disk_points(4096, 1.0, rng)
+    prob = pm.Problem(ctx, "disk", modes, prec=prec)
+    V = np_(prob.velocity(u, X))
+    ref = orc.velocity("disk", modes, u, X)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert np.max(np.abs(V - ref)) <= tol * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_normals_match_oracle(pm, ctx, orc, prec):
+    rng = np.random.default_rng(1)
+    n = rng.integers(0, 10**6, 50000)
+    i = rng.integers(0, 2**32, 50000, dtype=np.uint64).astype(np.uint32)
+    j = rng.integers(0, 49, 50000).astype(np.uint32)
+    prob = pm.Problem(ctx, "torus", W.torus_modes(1), theta0=W.fld("zero"), prec=prec)
+    Z = np_(prob.normals(n, i.astype(np.int64), j.astype(np.int64), seed=0xDEADBEEF12345))
+    ref = orc.normals(0xDEADBEEF12345, n.astype(np.uint64), i, j)
+    tol = 1e-13 if prec == "fp64" else 2e-5
+    assert np.max(np.abs(Z - ref)) <= tol * 6
+
+
+# ---------------------------------------------------------------------------
+# P1: teacher-forced steps
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("wl_name,prec,tol", [("torus-k2-fp64", "fp64", 1e-13),
+                                              ("torus-k2-fp64", "fp32", 1e-6),
+                                              ("torus-k6-fp32", "fp32", 1e-6),
+                                              ("torus-k6-fp32", "fp64", 1e-13)])
+def test_teacher_forced_steps(pm, ctx, orc, wl_name, prec, tol):
+    wl = W.WORKLOADS[wl_name]()
+    dte = wl.T / wl.n_steps
+    rows = []
+    for j in range(min(wl.n_obs, 4)):
+        for i in range(16):
+            P = orc.path("torus", wl.modes, wl.u, wl.kappa, dte, wl.seed, i, j, wl.obs[j], wl.n_steps)
+            for n in range(0, wl.n_steps, 7):
+                rows.append((P[n], P[n + 1], n, i, j))
+    X = np.array([r[0] for r in rows])
+    Yref = np.array([r[1] for r in rows])
+    n = np.array([r[2] for r in rows])
+    i = np.array([r[3] for r in rows])
+    j = np.array([r[4] for r in rows])
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec=prec)
+    Y = np_(prob.step(wl.u, X, n, i, j, wl.kappa, dte, wl.seed))
+    assert np.max(tdist(Y, Yref)) <= tol
+
+
+# ---------------------------------------------------------------------------
+# P2 / P3: full paths
+# ---------------------------------------------------------------------------
+
+def test_fp64_paths_and_means_match_oracle(pm, ctx, orc):
+    wl = W.time_small()
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp64")
+    m, v, ep = prob.observe_time(wl.u, wl.obs, wl.kappa, wl.T, wl.dt, wl.n_particles, wl.seed, endpoints=True)
+    pay, ep_ref = orc.observe_time_payoffs(wl.modes, wl.u, wl.theta0, wl.obs, wl.kappa, wl.T, wl.dt,
+                                           wl.n_particles, wl.seed, endpoints=True)
+    assert np.max(tdist(np_(ep), ep_ref)) <= 1e-12
+    mr, vr = orc.mean_var(pay)
+    assert np.max(np.abs(np_(m) - mr)) <= 1e-12
+    assert np.max(np.abs(np_(v) - vr)) <= 1e-12 * np.max(vr)
+
+
+def test_fp32_paths_small_workload(pm, ctx, orc):
+    wl = W.time_small()
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+    m, v, ep = prob.observe_time(wl.u, wl.obs, wl.kappa, wl.T, wl.dt, wl.n_particles, wl.seed, endpoints=True)
+    pay, ep_ref = orc.observe_time_payoffs(wl.modes, wl.u, wl.theta0, wl.obs, wl.kappa, wl.T, wl.dt,
+                                           wl.n_particles, wl.seed, endpoints=True)
+    d = np.max(tdist(np_(ep), ep_ref), axis=-1).ravel()
+    print("fp32 small-workload endpoint error: median %.2e p99 %.2e max %.2e"
+          % (np.median(d), np.quantile(d, 0.99), d.max()))
+    assert np.quantile(d, 0.99) <= 1e-5
+    # P4: paired mean test on the same streams
+    e_gpu = theta0_numpy(wl.theta0, np_(ep))
+    dd = e_gpu - pay
+    se = dd.std(axis=1, ddof=1) / math.sqrt(dd.shape[1]) + 1e-300
+    assert np.all(np.abs(np_(m) - pay.mean(axis=1)) <= 4 * se + 1e-12)
+
+
+def test_fp32_short_horizon_paths_main_workload(pm, ctx, orc):
+    wl = W.time_main()
+    T = 25 * wl.dt
+    Np = 256
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+    m, v, ep = prob.observe_time(wl.u, wl.obs, wl.kappa, T, wl.dt, Np, wl.seed, endpoints=True)
+    _, ep_ref = orc.observe_time_payoffs(wl.modes, wl.u, wl.theta0, wl.obs, wl.kappa, T, wl.dt, Np,
+                                         wl.seed, endpoints=True)
+    d = np.max(tdist(np_(ep), ep_ref), axis=-1).ravel()
+    print("fp32 25-step endpoint error: median %.2e p99 %.2e max %.2e" % (np.median(d), np.quantile(d, 0.99), d.max()))
+    assert np.quantile(d, 0.99) <= 1e-5
+
+
+def test_fp32_zero_flow_full_horizon(pm, ctx, orc):
+    wl = W.time_main()
+    u0 = np.zeros_like(wl.u)
+    Np = 200
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+    _, _, ep = prob.observe_time(u0, wl.obs[:8], wl.kappa, wl.T, wl.dt, Np, wl.seed, endpoints=True)
+    _, ep_ref = orc.observe_time_payoffs(wl.modes, u0, wl.theta0, wl.obs[:8], wl.kappa, wl.T, wl.dt, Np,
+                                         wl.seed, endpoints=True)
+    assert np.max(tdist(np_(ep), ep_ref)) <= 1e-5
+
+
+def test_fp32_means_main_workload_paired(pm, ctx, orc):
+    """Main workload (49 points, 1000 steps), 512 particles per point: the
+    per-path endpoints have decorrelated by T = 1, so this is the 3-SE test."""
+    wl = W.time_main()
+    Np = 512
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+    m, v, ep = prob.observe_time(wl.u, wl.obs, wl.kappa, wl.T, wl.dt, Np, wl.seed, endpoints=True)
+    pay, ep_ref = orc.observe_time_payoffs(wl.modes, wl.u, wl.theta0, wl.obs, wl.kappa, wl.T, wl.dt, Np,
+                                           wl.seed, endpoints=True)
+    e_gpu = theta0_numpy(wl.theta0, np_(ep))
+    # the GPU's own payoff and reduction reproduce the mean of its paths
+    assert np.max(np.abs(np_(m) - e_gpu.mean(axis=1))) <= 1e-12
+    dd = e_gpu - pay
+    se = dd.std(axis=1, ddof=1) / math.sqrt(Np) + 1e-300
+    z = np.abs(dd.mean(axis=1)) / se
+    assert np.sum(z > 3) <= 2 and np.all(z < 4.5), z
+
+
+def test_full_size_means_against_oracle_subsample(pm, ctx, orc):
+    """Main workload at full size (49 x 1e5 x 1000) in the benchmark's launch
+    configuration; the oracle runs the first 400 particles of every point."""
+    wl = W.time_main()
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+    m, v = prob.observe_time(wl.u, wl.obs, wl.kappa, wl.T, wl.dt, wl.n_particles, wl.seed)
+    ctx.sync(raise_on_flags=True)
+    mr, vr = orc.observe_time(wl.modes, wl.u, wl.theta0, wl.obs, wl.kappa, wl.T, wl.dt, 400, wl.seed)
+    se = np.sqrt(vr / 400 + np_(v) / wl.n_particles)
+    z = np.abs(np_(m) - mr) / se
+    assert np.sum(z > 3) <= 2 and np.all(z < 4.5), z
+    # variances agree to sampling accuracy
+    assert np.all(np.abs(np_(v) - vr) <= 6 * vr * math.sqrt(2 / 400) + 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# determinism, batching, edge cases
+# ---------------------------------------------------------------------------
+
+def test_bitwise_identical_across_launch_shapes(pm, ctx):
+    wl = W.time_main()
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+    res = []
+    for ppl, src in ((1, 0), (2, 0), (4, 0), (1, 1), (2, 1), (4, 1)):
+        ctx.set_tuning(ppl, src)
+        m, v = prob.observe_time(wl.u, wl.obs, wl.kappa, 0.2, wl.dt, 3000, wl.seed)
+        res.append((np_(m), np_(v)))
+    ctx.set_tuning(0, 0)
+    m0, v0 = prob.observe_time(wl.u, wl.obs, wl.kappa, 0.2, wl.dt, 3000, wl.seed)
+    for m, v in res:
+        assert np.array_equal(m, np_(m0)) and np.array_equal(v, np_(v0))
+
+
+def test_batch_equals_separate_calls_bitwise(pm, ctx):
+    wl = W.batch_main(n_u=5, lo=50, hi=3000)
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+    T = 0.1
+    mb, vb = prob.observe_time_batch(wl.u, wl.n_particles, wl.seed, wl.obs, wl.kappa, T, wl.dt)
+    for b in range(5):
+        m, v = prob.observe_time(wl.u[b], wl.obs, wl.kappa, T, wl.dt, int(wl.n_particles[b]), int(wl.seed[b]))
+        assert np.array_equal(np_(m), np_(mb[b])) and np.array_equal(np_(v), np_(vb[b]))
+
+
+@pytest.mark.parametrize("Np", [1, 63, 64, 65, 129])
+def test_ragged_particle_counts_fp64(pm, ctx, orc, Np):
+    wl = W.time_small()
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp64")
+    T = 0.013  # 13 steps: odd step count
+    m, v, ep = prob.observe_time(wl.u, wl.obs, wl.kappa, T, wl.dt, Np, 9, endpoints=True)
+    pay, ep_ref = orc.observe_time_payoffs(wl.modes, wl.u, wl.theta0, wl.obs, wl.kappa, T, wl.dt, Np, 9,
+                                           endpoints=True)
+    assert np.max(tdist(np_(ep), ep_ref)) <= 1e-12
+    mr, vr = orc.mean_var(pay)
+    assert np.allclose(np_(m), mr, rtol=0, atol=1e-12)
+    if Np > 1:
+        assert np.allclose(np_(v), vr, rtol=1e-10, atol=1e-14)
+    else:
+        assert np.all(np_(v) == 0)
+
+
+def test_empty_mode_table_is_pure_diffusion(pm, ctx, orc):
+    prob = pm.Problem(ctx, "torus", np.zeros((0, 2), np.int32), theta0=W.fld("sinsin", [1.0]), prec="fp64")
+    obs = np.array([[0.1, 0.3], [0.7, 0.2]])
+    m, v, ep = prob.observe_time(np.zeros(0), obs, 0.05, 0.1, 1e-3, 300, 4, endpoints=True)
+    pay, ep_ref = orc.observe_time_payoffs(np.zeros((0, 2), np.int32), np.zeros(0), W.fld("sinsin", [1.0]), obs,
+                                           0.05, 0.1, 1e-3, 300, 4, endpoints=True)
+    assert np.max(tdist(np_(ep), ep_ref)) <= 1e-12
+
+
+def test_invalid_arguments_raise(pm, ctx):
+    wl = W.time_small()
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp64")
+    for bad in (dict(kappa=-1.0), dict(T=0.0), dict(dt=0.0), dict(n_particles=0)):
+        kw = dict(kappa=wl.kappa, T=wl.T, dt=wl.dt, n_particles=10)
+        kw.update(bad)
+        with pytest.raises(pm.PMError) as e:
+            prob.observe_time(wl.u, wl.obs, kw["kappa"], kw["T"], kw["dt"], kw["n_particles"], 1)
+        assert e.value.status == pm.PM_EINVAL
+    with pytest.raises(pm.PMError):
+        pm.Problem(ctx, "torus", np.array([[9, 0]], np.int32), theta0=wl.theta0)
+    dprob = pm.Problem(ctx, "disk", W.disk_modes())
+    with pytest.raises(pm.PMError):
+        dprob.observe_time(np.zeros(64), wl.obs, 0.1, 1.0, 0.1, 10, 1)
+    assert ctx.sync() == pm.PM_OK

@@ -195,13 +195,16 @@ def time_main(seed: int = WORKLOAD_SEED, n_particles: int = 100_000) -> Workload
 def dirichlet_main(seed: int = WORKLOAD_SEED, n_particles: int = 50_000,
                    prec: str = "fp32") -> Workload:
     """Unit disk, psi = (1-|x|^2)^2 * (64-coefficient Fourier series), kappa 0.02,
-    g = cos 3 theta, f = 1, 25 uniform points in r<=0.8 x 5e4 particles, dt = 1e-4."""
+    g = cos 3 theta, 25 uniform points in r<=0.8 x 5e4 particles, dt = 1e-4.
+
+    The workload reads g(X_tau) + int_0^tau 1 ds.  Theorem 3.2's payoff is
+    g(X_tau) - int f, so that output is the paper's theta with source f = -1."""
     rng = np.random.default_rng([seed, 3])
     modes = disk_modes()
     u = draw_prior(modes, rng)
     obs = uniform_disk_points(25, 0.8, rng)
     return Workload("disk-dirichlet", "disk", modes, u, obs, kappa=0.02, dt=1e-4,
-                    n_particles=n_particles, seed=3, prec=prec, f=fld("const", [1.0]),
+                    n_particles=n_particles, seed=3, prec=prec, f=fld("const", [-1.0]),
                     g=fld("cos_m_theta", [3.0]), max_steps=20_000_000)
 
 
