@@ -10,8 +10,10 @@ libpm.so is missing -- there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -35,6 +37,17 @@ class PMError(RuntimeError):
 
 
 _LIBH = None
+_LIVE_PROBLEMS = weakref.WeakSet()
+_LIVE_CONTEXTS = weakref.WeakSet()
+
+
+@atexit.register
+def release_all():
+    """Destroy every live library object (problems first, then contexts)."""
+    for p in list(_LIVE_PROBLEMS):
+        p.close()
+    for c in list(_LIVE_CONTEXTS):
+        c.close()
 
 
 class _Field(C.Structure):
@@ -69,9 +82,6 @@ def _declare(L):
     L.pm_normals.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp, _u64, _vp]
     L.pm_sync.argtypes = [_vp]
     L.pm_last_kernel_stats.argtypes = [_vp, C.POINTER(_d), C.POINTER(_d)]
-    for name in ("pm_graph_create", "pm_graph_launch", "pm_graph_destroy"):
-        if hasattr(L, name):
-            pass
     return L
 
 
@@ -104,7 +114,7 @@ def _dev(x, dtype, device):
     if isinstance(x, torch.Tensor):
         t = x.to(device=device, dtype=dtype)
     else:
-        t = torch.as_tensor(np.asarray(x), dtype=dtype, device=device)
+        t = torch.as_tensor(np.array(x), dtype=dtype, device=device)
     return t.contiguous()
 
 
@@ -132,6 +142,8 @@ class Context:
         st = _lib().pm_create(C.byref(h), device, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
         _check(st, "pm_create")
         self.h = h
+        self._problems = weakref.WeakSet()
+        _LIVE_CONTEXTS.add(self)
 
     def bind_stream(self):
         torch = _torch()
@@ -152,7 +164,10 @@ class Context:
         return ms.value, steps.value
 
     def close(self):
+        """Destroy the context; its problems are destroyed first."""
         if getattr(self, "h", None):
+            for p in list(getattr(self, "_problems", ())):
+                p.close()
             _lib().pm_destroy(self.h)
             self.h = None
 
@@ -182,6 +197,8 @@ class Problem:
             C.byref(th.s) if th is not None else None, {"fp32": FP32, "fp64": FP64}[prec])
         _check(st, "pm_problem_create")
         self.h = h
+        ctx._problems.add(self)
+        _LIVE_PROBLEMS.add(self)
 
     def close(self):
         if getattr(self, "h", None):

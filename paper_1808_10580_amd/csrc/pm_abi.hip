@@ -38,6 +38,8 @@ struct pm_ctx {
     size_t exitp_cap = 0;
     void *integ = nullptr;
     size_t integ_cap = 0;
+    void *nsteps = nullptr;
+    size_t nsteps_cap = 0;
     void *meta = nullptr;
     size_t meta_cap = 0;
     int64_t *h_meta = nullptr;  // pinned staging for batch metadata
@@ -49,6 +51,11 @@ struct pm_ctx {
     double last_steps = 0.0;
     int ppl = 0;  // 0 = default
     int src = 0;
+    // Lifetime: the caller's handle plus one reference per live problem.
+    // pm_destroy releases the device resources at once; the struct itself is
+    // freed with the last reference, so problems may be destroyed after it.
+    int refs = 1;
+    bool closed = false;
 };
 
 struct pm_problem {
@@ -118,6 +125,18 @@ int to_field(const pm_field *f, FieldArg *out)
 
 int64_t n_steps_of(double T, double dt) { return (int64_t)std::ceil(T / dt - 1e-9); }
 
+// dt as hi + lo in the particle precision, and sqrt(2 kappa dt) (eq. euler with
+// sigma = sqrt(2 kappa) I).
+template <typename T>
+StepConsts<T> step_consts(double dt, double kappa)
+{
+    StepConsts<T> c;
+    c.dth = (T)dt;
+    c.dtl = (T)(dt - (double)c.dth);
+    c.sq = (T)std::sqrt(2.0 * kappa * dt);
+    return c;
+}
+
 template <typename T>
 int fold(pm_ctx *c, const pm_problem *p, const double *u, int n_sets, int64_t u_stride, T **coef_out,
          int64_t *stride_out)
@@ -164,13 +183,12 @@ int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
     a.n_obs = n_obs;
     a.n_u = n_u;
     a.n_steps = Nt;
-    a.dt = (T)dte;
-    a.sq = (T)std::sqrt(2.0 * kappa * dte);
+    a.sc = step_consts<T>(dte, kappa);
     a.v0x = (T)p->v0[0];
     a.v0y = (T)p->v0[1];
     a.queue = c->d_queue;
 
-    PayArgs<T> pa{};
+    PayArgs pa{};
     pa.n_u = n_u;
     pa.theta0 = p->theta0;
     pa.endpoints = endpoints;
@@ -240,9 +258,9 @@ int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
     }
     st = ensure(c, &c->part, &c->part_cap, (size_t)total_chunks * 3 * sizeof(double));
     if (st) return st;
-    st = ensure(c, &c->states, &c->states_cap, (size_t)total_chunks * 64 * 2 * sizeof(T));
+    st = ensure(c, &c->states, &c->states_cap, (size_t)total_chunks * 64 * 2 * sizeof(double));
     if (st) return st;
-    a.states = (T *)c->states;
+    a.states = (double *)c->states;
     pa.states = a.states;
     pa.n_chunks = total_chunks;
     pa.partials = (double *)c->part;
@@ -254,7 +272,7 @@ int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
     PM_HIP(hipEventRecord(c->ev1, c->stream));
     c->timed = true;
     c->last_steps = steps;
-    if (launch_time_payoff<T>(pa, c->stream) != hipSuccess) return PM_EDEVICE;
+    if (launch_time_payoff(pa, c->stream) != hipSuccess) return PM_EDEVICE;
     if (launch_finalize(fa, n_u * n_obs, c->stream) != hipSuccess) return PM_EDEVICE;
     return PM_OK;
 }
@@ -273,6 +291,7 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     if ((st = ensure(c, &c->pay, &c->pay_cap, total * sizeof(double)))) return st;
     if ((st = ensure(c, &c->tau, &c->tau_cap, total * sizeof(double)))) return st;
     if ((st = ensure(c, &c->integ, &c->integ_cap, total * sizeof(double)))) return st;
+    if ((st = ensure(c, &c->nsteps, &c->nsteps_cap, total * sizeof(double)))) return st;
     if ((st = ensure(c, &c->exitp, &c->exitp_cap, 2 * total * sizeof(double)))) return st;
     if ((st = ensure(c, &c->capped, &c->capped_cap, total))) return st;
     const int64_t cpo = (np + 63) / 64;
@@ -302,15 +321,14 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     a.total = total;
     a.seed = seed;
     a.max_steps = max_steps;
-    a.dt = (T)dt;
+    a.sc = step_consts<T>(dt, kappa);
     a.dtd = dt;
-    a.sq = (T)std::sqrt(2.0 * kappa * dt);
     a.v0x = (T)p->v0[0];
     a.v0y = (T)p->v0[1];
     a.f = fk == 0 ? fpoly : f;
     a.exitp = (double *)c->exitp;
     a.integ = (double *)c->integ;
-    a.tau = (double *)c->tau;
+    a.nsteps = (double *)c->nsteps;
     a.capped = (unsigned char *)c->capped;
     a.queue = c->d_queue;
 
@@ -327,14 +345,15 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     pa.g = g;
     pa.exitp = a.exitp;
     pa.integ = a.integ;
-    pa.tau = a.tau;
+    pa.nsteps = a.nsteps;
+    pa.tau = (double *)c->tau;
     pa.capped = a.capped;
     pa.pay = (double *)c->pay;
     pa.paths = paths;
     pa.flags = c->d_flags;
     if (launch_dir_payoff(pa, c->stream) != hipSuccess) return PM_EDEVICE;
     if (launch_chunk_reduce(pa.pay, np, n_obs, (double *)c->part, c->d_flags, c->stream)) return PM_EDEVICE;
-    if (launch_chunk_reduce(a.tau, np, n_obs, (double *)c->part2, c->d_flags, c->stream)) return PM_EDEVICE;
+    if (launch_chunk_reduce(pa.tau, np, n_obs, (double *)c->part2, c->d_flags, c->stream)) return PM_EDEVICE;
     FinalArgs fa{};
     fa.n_obs = n_obs;
     fa.cpo = cpo;
@@ -352,6 +371,13 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
 }
 
 bool bad_ptr(const void *p) { return p == nullptr; }
+
+void ctx_release(pm_ctx *c)
+{
+    if (--c->refs == 0) delete c;
+}
+
+bool ctx_ok(const pm_ctx *c, const pm_problem *p) { return c && p && p->ctx == c && !c->closed; }
 
 }  // namespace
 
@@ -403,30 +429,31 @@ int pm_create(pm_ctx **out, int device, void *stream)
 
 void pm_destroy(pm_ctx *c)
 {
-    if (!c) return;
+    if (!c || c->closed) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     void *bufs[] = {c->d_flags, c->d_queue, c->coef, c->part, c->part2, c->pay, c->tau, c->capped,
-                    c->meta, c->states, c->exitp, c->integ};
+                    c->meta, c->states, c->exitp, c->integ, c->nsteps};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->h_meta) (void)hipHostFree(c->h_meta);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->meta_ev) (void)hipEventDestroy(c->meta_ev);
-    delete c;
+    c->closed = true;
+    ctx_release(c);
 }
 
 int pm_set_stream(pm_ctx *c, void *stream)
 {
-    if (!c) return PM_EINVAL;
+    if (!c || c->closed) return PM_EINVAL;
     c->stream = (hipStream_t)stream;
     return PM_OK;
 }
 
 int pm_set_tuning(pm_ctx *c, int ppl, int src)
 {
-    if (!c) return PM_EINVAL;
+    if (!c || c->closed) return PM_EINVAL;
     if (!(ppl == 0 || ppl == 1 || ppl == 2 || ppl == 4)) return PM_EINVAL;
     if (!(src == 0 || src == 1)) return PM_EINVAL;
     c->ppl = ppl;
@@ -439,6 +466,7 @@ int pm_problem_create(pm_ctx *c, pm_problem **out, int domain, int n_modes, cons
 {
     if (!c || !out) return PM_EINVAL;
     *out = nullptr;
+    if (c->closed) return PM_EINVAL;
     if (domain != PM_TORUS && domain != PM_DISK) return PM_EINVAL;
     if (prec != PM_FP32 && prec != PM_FP64) return PM_EINVAL;
     if (n_modes < 0 || (n_modes > 0 && !k)) return PM_EINVAL;
@@ -481,6 +509,7 @@ int pm_problem_create(pm_ctx *c, pm_problem **out, int domain, int n_modes, cons
         delete p;
         return PM_EDEVICE;
     }
+    c->refs++;
     *out = p;
     return PM_OK;
 }
@@ -488,10 +517,14 @@ int pm_problem_create(pm_ctx *c, pm_problem **out, int domain, int n_modes, cons
 void pm_problem_destroy(pm_problem *p)
 {
     if (!p) return;
-    (void)hipSetDevice(p->ctx->device);
-    (void)hipStreamSynchronize(p->ctx->stream);
+    pm_ctx *c = p->ctx;
+    (void)hipSetDevice(c->device);
+    // the context's stream may already be gone once the context is closed
+    if (!c->closed) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
     if (p->d_k) (void)hipFree(p->d_k);
     delete p;
+    ctx_release(c);
 }
 
 static int check_time_args(double kappa, double T, double dt)
@@ -507,7 +540,7 @@ int pm_observe_time(pm_ctx *c, const pm_problem *p, const double *u, const doubl
                     double kappa, double T, double dt, int64_t np, uint64_t seed, double *mean,
                     double *var, double *endpoints)
 {
-    if (!c || !p || p->ctx != c) return PM_EINVAL;
+    if (!ctx_ok(c, p)) return PM_EINVAL;
     if (p->domain != PM_TORUS || !p->has_theta0) return PM_EINVAL;
     if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(obs) || bad_ptr(mean) || bad_ptr(var)) return PM_EINVAL;
     if (n_obs < 1) return PM_EINVAL;
@@ -523,7 +556,7 @@ int pm_observe_time_batch(pm_ctx *c, const pm_problem *p, int n_u, const double 
                           const int64_t *nps, const uint64_t *seeds, const double *obs, int n_obs,
                           double kappa, double T, double dt, double *mean, double *var)
 {
-    if (!c || !p || p->ctx != c) return PM_EINVAL;
+    if (!ctx_ok(c, p)) return PM_EINVAL;
     if (p->domain != PM_TORUS || !p->has_theta0) return PM_EINVAL;
     if (n_u < 1 || !nps || !seeds) return PM_EINVAL;
     if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(obs) || bad_ptr(mean) || bad_ptr(var)) return PM_EINVAL;
@@ -542,7 +575,7 @@ int pm_observe_dirichlet(pm_ctx *c, const pm_problem *p, const double *u, const 
                          int64_t np, uint64_t seed, int64_t max_steps, double *mean, double *var,
                          double *tau_mean, double *tau_var, int64_t *n_capped, double *paths)
 {
-    if (!c || !p || p->ctx != c) return PM_EINVAL;
+    if (!ctx_ok(c, p)) return PM_EINVAL;
     if (p->domain != PM_DISK) return PM_EINVAL;
     if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(obs) || bad_ptr(mean) || bad_ptr(var) ||
         bad_ptr(tau_mean) || bad_ptr(tau_var) || bad_ptr(n_capped))
@@ -565,7 +598,7 @@ int pm_step(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, cons
             const uint64_t *n, const uint32_t *i, const uint32_t *j, double kappa, double dt,
             uint64_t seed, double *Y)
 {
-    if (!c || !p || p->ctx != c) return PM_EINVAL;
+    if (!ctx_ok(c, p)) return PM_EINVAL;
     if (count < 0) return PM_EINVAL;
     if (count == 0) return PM_OK;
     if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(X) || bad_ptr(n) || bad_ptr(i) || bad_ptr(j) || bad_ptr(Y))
@@ -587,8 +620,7 @@ int pm_step(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, cons
         a.i = i;
         a.j = j;
         a.seed = seed;
-        a.dt = (T)dt;
-        a.sq = (T)std::sqrt(2.0 * kappa * dt);
+        a.sc = step_consts<T>(dt, kappa);
         a.v0x = (T)p->v0[0];
         a.v0y = (T)p->v0[1];
         a.Y = Y;
@@ -599,7 +631,7 @@ int pm_step(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, cons
 
 int pm_velocity(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, const double *X, double *V)
 {
-    if (!c || !p || p->ctx != c) return PM_EINVAL;
+    if (!ctx_ok(c, p)) return PM_EINVAL;
     if (count < 0) return PM_EINVAL;
     if (count == 0) return PM_OK;
     if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(X) || bad_ptr(V)) return PM_EINVAL;
@@ -621,7 +653,7 @@ int pm_velocity(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, 
 int pm_normals(pm_ctx *c, const pm_problem *p, int64_t count, const uint64_t *n, const uint32_t *i,
                const uint32_t *j, uint64_t seed, double *Z)
 {
-    if (!c || !p || p->ctx != c) return PM_EINVAL;
+    if (!ctx_ok(c, p)) return PM_EINVAL;
     if (count < 0) return PM_EINVAL;
     if (count == 0) return PM_OK;
     if (bad_ptr(n) || bad_ptr(i) || bad_ptr(j) || bad_ptr(Z)) return PM_EINVAL;
@@ -633,7 +665,7 @@ int pm_normals(pm_ctx *c, const pm_problem *p, int64_t count, const uint64_t *n,
 
 int pm_sync(pm_ctx *c)
 {
-    if (!c) return PM_EINVAL;
+    if (!c || c->closed) return PM_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return PM_EDEVICE;
     if (hipGetLastError() != hipSuccess) return PM_EDEVICE;
@@ -647,7 +679,7 @@ int pm_sync(pm_ctx *c)
 
 int pm_last_kernel_stats(pm_ctx *c, double *ms, double *steps)
 {
-    if (!c || !ms || !steps) return PM_EINVAL;
+    if (!c || c->closed || !ms || !steps) return PM_EINVAL;
     if (!c->timed) return PM_EINVAL;
     float f = 0.f;
     if (hipEventElapsedTime(&f, c->ev0, c->ev1) != hipSuccess) return PM_EDEVICE;

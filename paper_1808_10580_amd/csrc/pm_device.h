@@ -121,6 +121,64 @@ __device__ __forceinline__ void trig_basis(T s, T *phi)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Particle coordinate and the Euler-Maruyama update of eq. (euler),
+//   X <- X - v(X) dt + sqrt(2 kappa dt) xi.
+// FP64: a double, updated as the oracle does.
+// FP32: an unevaluated sum hi + lo of two floats, renormalised after every
+// update (|lo| <= ulp(hi)/2), so the state carries no FP32 rounding drift;
+// the velocity is evaluated at hi.  dt is split the same way so that its
+// FP32 rounding does not act as a coherent bias on the drift.  On the torus
+// hi is kept in [-1/2, 1/2] by subtracting rint(hi), which is exact
+// (Sterbenz) because one step moves a particle by far less than 1/2.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct StepConsts {
+    T dth, dtl, sq;
+};
+
+template <typename T>
+struct Coord;
+
+template <>
+struct Coord<double> {
+    double v;
+    __device__ __forceinline__ void set(double x) { v = x; }
+    __device__ __forceinline__ double at() const { return v; }
+    __device__ __forceinline__ double value() const { return v; }
+    __device__ __forceinline__ void advance(double vel, double z, const StepConsts<double> &c)
+    {
+        v = __builtin_fma(-c.dth, vel, v);
+        v = __builtin_fma(c.sq, z, v);
+    }
+    __device__ __forceinline__ void wrap() { v -= floor(v); }
+};
+
+template <>
+struct Coord<float> {
+    float hi, lo;
+    __device__ __forceinline__ void set(double x)
+    {
+        hi = (float)x;
+        lo = (float)(x - (double)hi);
+    }
+    __device__ __forceinline__ float at() const { return hi; }
+    __device__ __forceinline__ double value() const { return (double)hi + (double)lo; }
+    __device__ __forceinline__ void advance(float vel, float z, const StepConsts<float> &c)
+    {
+        float d = __builtin_fmaf(-c.dtl, vel, c.sq * z);
+        d = __builtin_fmaf(-c.dth, vel, d);
+        // two-sum hi + d = s + e exactly, then fold lo in and renormalise
+        const float s = hi + d;
+        const float bb = s - hi;
+        float e = (hi - (s - bb)) + (d - bb);
+        e += lo;
+        hi = s + e;
+        lo = e - (hi - s);
+    }
+    __device__ __forceinline__ void wrap() { hi -= __builtin_rintf(hi); }
+};
+
 // Pointer into the constant address space: uniform loads through it become
 // scalar-cache loads (s_load) whose results feed VALU ops as SGPR operands.
 template <typename T>

@@ -40,14 +40,14 @@ struct TimeArgs {
     const int64_t *chunk_off;  // device [n_u+1]
     int64_t n_tasks;
     int64_t n_steps;
-    T dt, sq, v0x, v0y;
-    T *states;  // [total chunks][64][2] final positions
+    StepConsts<T> sc;
+    T v0x, v0y;
+    double *states;  // [total chunks][64][2] final positions
     unsigned long long *queue;
 };
 
-template <typename T>
 struct PayArgs {
-    const T *states;
+    const double *states;
     int64_t n_chunks;
     int n_u;
     int64_t np0;
@@ -68,12 +68,13 @@ struct DirArgs {
     int64_t total;
     uint64_t seed;
     int64_t max_steps;
-    T dt, sq, v0x, v0y;
+    StepConsts<T> sc;
+    T v0x, v0y;
     double dtd;
     FieldArg f;
     double *exitp;  // [total][2]
-    double *integ;  // [total] int_0^tau f dt
-    double *tau;    // [total] exit time
+    double *integ;   // [total] int_0^tau f dt
+    double *nsteps;  // [total] steps taken (an exact integer)
     unsigned char *capped;
     unsigned long long *queue;
 };
@@ -84,9 +85,10 @@ struct DirPayArgs {
     FieldArg g;
     const double *exitp;
     const double *integ;
-    const double *tau;
+    const double *nsteps;
     const unsigned char *capped;
     double *pay;
+    double *tau;    // [total] exit time nsteps * dt
     double *paths;  // nullable
     unsigned *flags;
 };
@@ -112,7 +114,8 @@ struct StepArgs {
     const uint32_t *i;
     const uint32_t *j;
     uint64_t seed;
-    T dt, sq, v0x, v0y;
+    StepConsts<T> sc;
+    T v0x, v0y;
     double *Y;
 };
 
@@ -125,8 +128,7 @@ hipError_t launch_time(const TimeArgs<T> &a, int K, int ppl, int src, int n_cu, 
 template <typename T>
 hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int n_cu, hipStream_t st);
 hipError_t launch_dir_payoff(const DirPayArgs &a, hipStream_t st);
-template <typename T>
-hipError_t launch_time_payoff(const PayArgs<T> &a, hipStream_t st);
+hipError_t launch_time_payoff(const PayArgs &a, hipStream_t st);
 hipError_t launch_chunk_reduce(const double *vals, int64_t np, int n_obs, double *partials,
                                unsigned *flags, hipStream_t st);
 hipError_t launch_finalize(const FinalArgs &a, int n_groups, hipStream_t st);

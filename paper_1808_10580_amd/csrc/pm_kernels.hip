@@ -101,13 +101,6 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T>
-__device__ __forceinline__ T wrap01(T s);
-template <>
-__device__ __forceinline__ float wrap01<float>(float s) { return __builtin_amdgcn_fractf(s); }
-template <>
-__device__ __forceinline__ double wrap01<double>(double s) { return s - floor(s); }
-
 // Chunk statistics of the lanes' values: count, sum and the sum of squared
 // deviations from the chunk mean (two passes over the same fixed tree).
 __device__ __forceinline__ void chunk_stats(bool act, double e, double &cnt, double &s, double &m2)
@@ -175,7 +168,7 @@ __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
         }
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 
-        T x[PPL], y[PPL];
+        Coord<T> x[PPL], y[PPL];
         uint32_t pi[PPL], pj[PPL];
         bool act[PPL], cval[PPL];
         int64_t cix[PPL];
@@ -191,16 +184,16 @@ __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
             act[p] = cval[p] && i < np;
             pi[p] = (uint32_t)i;
             pj[p] = (uint32_t)j;
-            x[p] = (T)a.obs[2 * j];
-            y[p] = (T)a.obs[2 * j + 1];
+            x[p].set(a.obs[2 * j]);
+            y[p].set(a.obs[2 * j + 1]);
         }
 
         auto step = [&](const T (&z0)[PPL], const T (&z1)[PPL]) {
             T phx[PPL][B], phy[PPL][B];
 #pragma unroll
             for (int p = 0; p < PPL; ++p) {
-                trig_basis<T, K>(x[p], phx[p]);
-                trig_basis<T, K>(y[p], phy[p]);
+                trig_basis<T, K>(x[p].at(), phx[p]);
+                trig_basis<T, K>(y[p].at(), phy[p]);
             }
             T vx[PPL], vy[PPL];
             // The coefficients are re-read every step (LDS broadcast or
@@ -214,12 +207,10 @@ __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
             }
 #pragma unroll
             for (int p = 0; p < PPL; ++p) {
-                T nx = fma_(-a.dt, vx[p] + a.v0x, x[p]);
-                T ny = fma_(-a.dt, vy[p] + a.v0y, y[p]);
-                nx = fma_(a.sq, z0[p], nx);
-                ny = fma_(a.sq, z1[p], ny);
-                x[p] = wrap01<T>(nx);
-                y[p] = wrap01<T>(ny);
+                x[p].advance(vx[p] + a.v0x, z0[p], a.sc);
+                y[p].advance(vy[p] + a.v0y, z1[p], a.sc);
+                x[p].wrap();
+                y[p].wrap();
             }
         };
 
@@ -249,9 +240,9 @@ __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
             if (cval[p]) {
-                T *S = a.states + 2 * ((cb + cix[p]) * 64 + lane);
-                S[0] = x[p];
-                S[1] = y[p];
+                double *S = a.states + 2 * ((cb + cix[p]) * 64 + lane);
+                S[0] = x[p].value();
+                S[1] = y[p].value();
             }
         }
     }
@@ -259,8 +250,7 @@ __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
 
 // Payoff theta0(X_T) (FP64) of every particle and its chunk statistics.  One
 // wave per 64-particle chunk; the lane <-> particle map is that of k_time.
-template <typename T>
-__global__ __launch_bounds__(256) void k_time_payoff(const PayArgs<T> a)
+__global__ __launch_bounds__(256) void k_time_payoff(const PayArgs a)
 {
     const int lane = threadIdx.x & 63;
     const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -283,8 +273,8 @@ __global__ __launch_bounds__(256) void k_time_payoff(const PayArgs<T> a)
     const int64_t j = c / cpo, q = c - j * cpo;
     const int64_t i = q * 64 + lane;
     const bool act = i < np;
-    const T *S = a.states + 2 * (g * 64 + lane);
-    const double xd = (double)S[0], yd = (double)S[1];
+    const double *S = a.states + 2 * (g * 64 + lane);
+    const double xd = S[0] - floor(S[0]), yd = S[1] - floor(S[1]);
     double e = 0.0;
     if (act) e = field_eval(a.theta0, xd, yd);
     if (a.endpoints && act) {
@@ -333,7 +323,9 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
     const int lane = threadIdx.x & 63;
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     bool has = false, done = false;
-    T x = T(0), y = T(0);
+    Coord<T> x, y;
+    x.set(0.0);
+    y.set(0.0);
     double I = 0.0;
     int64_t n = 0, t = 0;
     uint32_t pi = 0, pj = 0;
@@ -342,7 +334,7 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
         a.exitp[2 * t] = ex;
         a.exitp[2 * t + 1] = ey;
         a.integ[t] = I;
-        a.tau[t] = (double)n * a.dtd;
+        a.nsteps[t] = (double)n;
         a.capped[t] = exited ? 0 : 1;
         has = false;
     };
@@ -350,18 +342,18 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
     auto substep = [&](T z0, T z1) {
         __asm__ volatile("" ::: "memory");
         T phx[B], phy[B];
-        trig_basis<T, K>(x, phx);
-        trig_basis<T, K>(y, phy);
+        const T xa = x.at(), ya = y.at();
+        trig_basis<T, K>(xa, phx);
+        trig_basis<T, K>(ya, phy);
         T vx, vy;
-        disk_velocity<T, K>(C, phx, phy, x, y, vx, vy);
-        T nx = fma_(-a.dt, vx + a.v0x, x);
-        T ny = fma_(-a.dt, vy + a.v0y, y);
-        nx = fma_(a.sq, z0, nx);
-        ny = fma_(a.sq, z1, ny);
+        disk_velocity<T, K>(C, phx, phy, xa, ya, vx, vy);
+        Coord<T> nx = x, ny = y;
+        nx.advance(vx + a.v0x, z0, a.sc);
+        ny.advance(vy + a.v0y, z1, a.sc);
         if (has) {
-            I += source_at<FK>(a.f, (double)x, (double)y) * a.dtd;  // left point
+            I += source_at<FK>(a.f, x.value(), y.value()) * a.dtd;  // left point
             n += 1;
-            const double nxd = (double)nx, nyd = (double)ny;
+            const double nxd = nx.value(), nyd = ny.value();
             const double r2 = nxd * nxd + nyd * nyd;
             if (r2 >= 1.0) {
                 const double r = sqrt(r2);
@@ -390,8 +382,8 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
                     t = tt;
                     pj = (uint32_t)(tt / a.np);
                     pi = (uint32_t)(tt - (int64_t)pj * a.np);
-                    x = (T)a.obs[2 * pj];
-                    y = (T)a.obs[2 * pj + 1];
+                    x.set(a.obs[2 * pj]);
+                    y.set(a.obs[2 * pj + 1]);
                     I = 0.0;
                     n = 0;
                     has = true;
@@ -420,12 +412,13 @@ __global__ __launch_bounds__(256) void k_dir_payoff(const DirPayArgs a)
     const bool capped = a.capped[t] != 0;
     const double pay = (capped ? 0.0 : field_eval(a.g, ex, ey)) - a.integ[t];
     a.pay[t] = pay;
+    a.tau[t] = a.nsteps[t] * a.dtd;
     if (a.paths) {
         double *P = a.paths + 4 * t;
         P[0] = ex;
         P[1] = ey;
         P[2] = pay;
-        P[3] = a.tau[t] / a.dtd;
+        P[3] = a.nsteps[t];
     }
     if (capped) atomicOr(a.flags, PM_FLAG_CAPPED);
     if (!isfinite(pay)) atomicOr(a.flags, PM_FLAG_NONFINITE);
@@ -589,7 +582,9 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= a.count) return;
-    const T x = (T)a.X[2 * e], y = (T)a.X[2 * e + 1];
+    Coord<T> x, y;
+    x.set(a.X[2 * e]);
+    y.set(a.X[2 * e + 1]);
     const uint64_t n = a.n[e];
     const U4 w = philox4x32_10((uint32_t)(n >> 1), a.i[e], a.j[e], 0u, (uint32_t)a.seed,
                                (uint32_t)(a.seed >> 32));
@@ -597,17 +592,16 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a)
     if ((n & 1) == 0) box_muller(w.x, w.y, z0, z1);
     else box_muller(w.z, w.w, z0, z1);
     T vx, vy;
-    velocity_at<T, K>(a.coef, a.domain, x, y, vx, vy);
-    T nx = fma_(-a.dt, vx + a.v0x, x);
-    T ny = fma_(-a.dt, vy + a.v0y, y);
-    nx = fma_(a.sq, z0, nx);
-    ny = fma_(a.sq, z1, ny);
+    velocity_at<T, K>(a.coef, a.domain, x.at(), y.at(), vx, vy);
+    x.advance(vx + a.v0x, z0, a.sc);
+    y.advance(vy + a.v0y, z1, a.sc);
+    double nx = x.value(), ny = y.value();
     if (a.domain == PM_TORUS) {
-        nx = wrap01<T>(nx);
-        ny = wrap01<T>(ny);
+        nx -= floor(nx);
+        ny -= floor(ny);
     }
-    a.Y[2 * e] = (double)nx;
-    a.Y[2 * e + 1] = (double)ny;
+    a.Y[2 * e] = nx;
+    a.Y[2 * e + 1] = ny;
 }
 
 template <typename T, int K>
@@ -617,8 +611,11 @@ __global__ __launch_bounds__(256) void k_velocity(const T *__restrict__ coef, in
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
+    Coord<T> x, y;
+    x.set(X[2 * e]);
+    y.set(X[2 * e + 1]);
     T vx, vy;
-    velocity_at<T, K>(coef, domain, (T)X[2 * e], (T)X[2 * e + 1], vx, vy);
+    velocity_at<T, K>(coef, domain, x.at(), y.at(), vx, vy);
     V[2 * e] = (double)(vx + v0x);
     V[2 * e + 1] = (double)(vy + v0y);
 }
@@ -743,15 +740,12 @@ hipError_t launch_dir_payoff(const DirPayArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_time_payoff(const PayArgs<T> &a, hipStream_t st)
+hipError_t launch_time_payoff(const PayArgs &a, hipStream_t st)
 {
     const int64_t blocks = (a.n_chunks + 3) / 4;
-    hipLaunchKernelGGL(k_time_payoff<T>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_time_payoff, dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
-template hipError_t launch_time_payoff<float>(const PayArgs<float> &, hipStream_t);
-template hipError_t launch_time_payoff<double>(const PayArgs<double> &, hipStream_t);
 
 hipError_t launch_chunk_reduce(const double *vals, int64_t np, int n_obs, double *partials,
                                unsigned *flags, hipStream_t st)

@@ -18,3 +18,14 @@ def orc():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _release_library_objects():
+    """Destroy every libpm object at the end of the session, while the HIP
+    runtime is fully alive, whatever tracebacks still reference them."""
+    yield
+    import sys
+    pm = sys.modules.get("paper_1808_10580_amd")
+    if pm is not None:
+        pm.release_all()
