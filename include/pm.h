@@ -51,6 +51,7 @@ extern "C" {
 
 typedef struct pm_ctx pm_ctx;
 typedef struct pm_problem pm_problem;
+typedef struct pm_graph pm_graph;
 
 enum pm_status {
     PM_OK = 0,
@@ -186,8 +187,45 @@ int pm_last_kernel_stats(pm_ctx *ctx, double *ms, double *particle_steps);
 const char *pm_strerror(int status);
 
 /* Kernel tuning knob for the time kernel: particles per lane (1, 2 or 4) and
- * coefficient source (0 = LDS, 1 = scalar cache); 0 = library default. */
+ * coefficient source (0 = LDS, 1 = scalar cache).  particles_per_lane = 0
+ * selects the autotuned choice for the problem's K, else 2 particles per lane.
+ * Every choice gives bitwise identical results. */
 int pm_set_tuning(pm_ctx *ctx, int particles_per_lane, int coef_source);
+
+/* Number of persistent 256-thread blocks per compute unit for the time kernel
+ * (0 = as many as occupancy allows). */
+int pm_set_blocks_per_cu(pm_ctx *ctx, int blocks_per_cu);
+
+/* Autotuner for the time kernel (Algorithm 1): times every particles-per-lane
+ * and coefficient-source variant on a probe of n_probe_steps steps with the
+ * given particle count and stores the fastest for this problem's K in the
+ * context (used whenever pm_set_tuning's particles_per_lane is 0).  Results
+ * are bitwise identical for every variant, so tuning never changes G(u).
+ * Synchronous.  Outputs (host, nullable): chosen particles per lane,
+ * coefficient source and the probe time in milliseconds. */
+int pm_autotune_time(pm_ctx *ctx, const pm_problem *p, const double *u, const double *obs_pts,
+                     int n_obs, double kappa, double dt, int64_t n_particles, uint64_t seed,
+                     int n_probe_steps, int *particles_per_lane, int *coef_source, double *probe_ms);
+
+/* Captured forward map.  Records the whole of one pm_observe_time_batch call
+ * (coefficient fold, persistent time kernel, payoff/chunk reduction and
+ * finalize; n_u = 1 is the single forward map) as a HIP graph with fixed
+ * arguments and a private workspace.  pm_graph_launch replays it on the
+ * context's current stream; every replay re-reads u and the observation
+ * points from the same device buffers, so an MCMC loop writes each proposal
+ * into u and replays (Section 4.1 runs long pCN chains of forward maps).
+ * Creation runs the map once eagerly (to size the workspace), then captures;
+ * it synchronises.  The graph keeps its context and problem alive; destroy
+ * it with pm_graph_destroy.  Replays report non-finite results through
+ * pm_sync(ctx).  Argument meaning as for pm_observe_time_batch. */
+int pm_graph_create_time(pm_ctx *ctx, const pm_problem *p, int n_u, const double *u,
+                         const int64_t *n_particles, const uint64_t *seeds, const double *obs_pts,
+                         int n_obs, double kappa, double T, double dt, double *mean, double *var,
+                         pm_graph **out);
+int pm_graph_launch(pm_graph *g);
+/* Particle-steps one replay executes. */
+int pm_graph_particle_steps(const pm_graph *g, double *steps);
+void pm_graph_destroy(pm_graph *g);
 
 #ifdef __cplusplus
 }

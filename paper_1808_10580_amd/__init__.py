@@ -43,7 +43,10 @@ _LIVE_CONTEXTS = weakref.WeakSet()
 
 @atexit.register
 def release_all():
-    """Destroy every live library object (problems first, then contexts)."""
+    """Destroy every live library object (graphs, problems, then contexts)."""
+    for c in list(_LIVE_CONTEXTS):
+        for g in list(getattr(c, "_graphs", ())):
+            g.close()
     for p in list(_LIVE_PROBLEMS):
         p.close()
     for c in list(_LIVE_CONTEXTS):
@@ -82,6 +85,15 @@ def _declare(L):
     L.pm_normals.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp, _u64, _vp]
     L.pm_sync.argtypes = [_vp]
     L.pm_last_kernel_stats.argtypes = [_vp, C.POINTER(_d), C.POINTER(_d)]
+    L.pm_set_blocks_per_cu.argtypes = [_vp, C.c_int]
+    L.pm_autotune_time.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _i64, _u64, C.c_int,
+                                   C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(_d)]
+    L.pm_graph_create_time.argtypes = [_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.c_int, _d, _d, _d,
+                                       _vp, _vp, C.POINTER(_vp)]
+    L.pm_graph_launch.argtypes = [_vp]
+    L.pm_graph_particle_steps.argtypes = [_vp, C.POINTER(_d)]
+    L.pm_graph_destroy.argtypes = [_vp]
+    L.pm_graph_destroy.restype = None
     return L
 
 
@@ -143,6 +155,7 @@ class Context:
         _check(st, "pm_create")
         self.h = h
         self._problems = weakref.WeakSet()
+        self._graphs = weakref.WeakSet()
         _LIVE_CONTEXTS.add(self)
 
     def bind_stream(self):
@@ -151,6 +164,9 @@ class Context:
 
     def set_tuning(self, particles_per_lane: int = 0, coef_source: int = 0):
         _check(_lib().pm_set_tuning(self.h, particles_per_lane, coef_source), "pm_set_tuning")
+
+    def set_blocks_per_cu(self, blocks_per_cu: int = 0):
+        _check(_lib().pm_set_blocks_per_cu(self.h, blocks_per_cu), "pm_set_blocks_per_cu")
 
     def sync(self, raise_on_flags: bool = False) -> int:
         st = _lib().pm_sync(self.h)
@@ -164,8 +180,10 @@ class Context:
         return ms.value, steps.value
 
     def close(self):
-        """Destroy the context; its problems are destroyed first."""
+        """Destroy the context; its graphs and problems are destroyed first."""
         if getattr(self, "h", None):
+            for g in list(getattr(self, "_graphs", ())):
+                g.close()
             for p in list(getattr(self, "_problems", ())):
                 p.close()
             _lib().pm_destroy(self.h)
@@ -197,11 +215,14 @@ class Problem:
             C.byref(th.s) if th is not None else None, {"fp32": FP32, "fp64": FP64}[prec])
         _check(st, "pm_problem_create")
         self.h = h
+        self._graphs = weakref.WeakSet()
         ctx._problems.add(self)
         _LIVE_PROBLEMS.add(self)
 
     def close(self):
         if getattr(self, "h", None):
+            for g in list(getattr(self, "_graphs", ())):
+                g.close()
             _lib().pm_problem_destroy(self.h)
             self.h = None
 
@@ -249,6 +270,25 @@ class Problem:
                                           float(T), float(dt), _ptr(mean), _ptr(var))
         _check(st, "pm_observe_time_batch")
         return mean, var
+
+    def autotune_time(self, u, obs, kappa, dt, n_particles, seed=1, n_probe_steps=100):
+        """Time every kernel variant on a probe and keep the fastest for this K."""
+        torch = _torch()
+        self.ctx.bind_stream()
+        ut = self._u(u)
+        ob = _dev(obs, torch.float64, self.ctx.device).reshape(-1, 2)
+        ppl, src, ms = C.c_int(), C.c_int(), C.c_double()
+        st = _lib().pm_autotune_time(self.ctx.h, self.h, _ptr(ut), _ptr(ob), ob.shape[0], float(kappa),
+                                     float(dt), int(n_particles), int(seed), int(n_probe_steps),
+                                     C.byref(ppl), C.byref(src), C.byref(ms))
+        _check(st, "pm_autotune_time")
+        return {"particles_per_lane": ppl.value, "coef_source": src.value, "probe_ms": ms.value}
+
+    def graph_time(self, u, obs, kappa, T, dt, n_particles, seeds) -> "Graph":
+        """Capture pm_observe_time_batch (n_u = len(n_particles)) as a replayable graph.
+        ``u`` and ``obs`` must be CUDA float64 tensors the caller keeps and updates
+        in place between replays; the graph's outputs are ``graph.mean``/``graph.var``."""
+        return Graph(self, u, obs, kappa, T, dt, n_particles, seeds)
 
     # -- Algorithm 2 -----------------------------------------------------------------
     def observe_dirichlet(self, u, f: dict, g: dict, obs, kappa, dt, n_particles, seed, max_steps,
@@ -312,6 +352,58 @@ class Problem:
         st = _lib().pm_normals(self.ctx.h, self.h, cnt, _ptr(nt), _ptr(it), _ptr(jt), int(seed), _ptr(Z))
         _check(st, "pm_normals")
         return Z
+
+
+class Graph:
+    """A captured forward map (pm_graph_create_time); replay() re-reads u and obs."""
+
+    def __init__(self, prob: Problem, u, obs, kappa, T, dt, n_particles, seeds):
+        torch = _torch()
+        ctx = prob.ctx
+        ctx.bind_stream()
+        if not (isinstance(u, torch.Tensor) and u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()):
+            raise TypeError("u must be a contiguous CUDA float64 tensor kept alive by the caller")
+        if not (isinstance(obs, torch.Tensor) and obs.is_cuda and obs.dtype == torch.float64 and obs.is_contiguous()):
+            raise TypeError("obs must be a contiguous CUDA float64 tensor kept alive by the caller")
+        nps = np.ascontiguousarray(np.atleast_1d(np.asarray(n_particles, dtype=np.int64)))
+        sds = np.ascontiguousarray(np.atleast_1d(np.asarray(seeds, dtype=np.uint64)))
+        n_u = int(nps.size)
+        n_obs = obs.numel() // 2
+        self.u, self.obs = u, obs
+        shape = (n_u, n_obs) if n_u > 1 else (n_obs,)
+        self.mean = torch.empty(shape, dtype=torch.float64, device=ctx.device)
+        self.var = torch.empty_like(self.mean)
+        h = C.c_void_p()
+        st = _lib().pm_graph_create_time(ctx.h, prob.h, n_u, _ptr(u), C.c_void_p(nps.ctypes.data),
+                                         C.c_void_p(sds.ctypes.data), _ptr(obs), n_obs, float(kappa),
+                                         float(T), float(dt), _ptr(self.mean), _ptr(self.var), C.byref(h))
+        _check(st, "pm_graph_create_time")
+        self.h = h
+        self.ctx = ctx
+        self.prob = prob
+        ctx._graphs.add(self)
+        prob._graphs.add(self)
+
+    def replay(self):
+        self.ctx.bind_stream()
+        _check(_lib().pm_graph_launch(self.h), "pm_graph_launch")
+        return self.mean, self.var
+
+    def particle_steps(self) -> float:
+        s = C.c_double()
+        _check(_lib().pm_graph_particle_steps(self.h, C.byref(s)), "pm_graph_particle_steps")
+        return s.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib().pm_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def n_steps(T: float, dt: float) -> int:

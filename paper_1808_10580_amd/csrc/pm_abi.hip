@@ -49,8 +49,12 @@ struct pm_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
     double last_steps = 0.0;
-    int ppl = 0;  // 0 = default
+    int ppl = 0;  // explicit tuning (0 = autotuned or default)
     int src = 0;
+    int bpc = 0;  // persistent blocks per CU (0 = occupancy limit)
+    int tune_ppl[PM_MAX_K + 1] = {0};  // autotuned choice per harmonic count K
+    int tune_src[PM_MAX_K + 1] = {0};
+    bool capturing = false;  // recording a graph: no timing events, no host waits
     // Lifetime: the caller's handle plus one reference per live problem.
     // pm_destroy releases the device resources at once; the struct itself is
     // freed with the last reference, so problems may be destroyed after it.
@@ -58,8 +62,20 @@ struct pm_ctx {
     bool closed = false;
 };
 
+struct pm_graph {
+    pm_ctx *owner = nullptr;
+    pm_ctx *priv = nullptr;  // private workspace: never reallocated by other calls
+    unsigned *priv_flags = nullptr;
+    pm_problem *prob = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double steps = 0.0;
+};
+
 struct pm_problem {
     pm_ctx *ctx = nullptr;
+    int refs = 1;  // the caller's handle plus one per graph that uses it
     int domain = PM_TORUS;
     int prec = PM_FP32;
     int n_modes = 0;
@@ -161,7 +177,21 @@ int fold(pm_ctx *c, const pm_problem *p, const double *u, int n_sets, int64_t u_
     return PM_OK;
 }
 
-int default_ppl(const pm_ctx *c) { return c->ppl ? c->ppl : 2; }
+// Particles per lane and coefficient source for the FP32 time kernel:
+// explicit setting, else the autotuned choice for this K, else 2 / LDS.
+void time_tuning(const pm_ctx *c, int K, int *ppl, int *src)
+{
+    if (c->ppl) {
+        *ppl = c->ppl;
+        *src = c->src;
+    } else if (c->tune_ppl[K]) {
+        *ppl = c->tune_ppl[K];
+        *src = c->tune_src[K];
+    } else {
+        *ppl = 2;
+        *src = c->src;
+    }
+}
 
 template <typename T>
 int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, const int64_t *nps,
@@ -175,7 +205,8 @@ int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
     int st = fold<T>(c, p, u, n_u, 2 * (int64_t)p->n_modes, &coef, &cstride);
     if (st) return st;
 
-    const int ppl = std::is_same<T, double>::value ? 1 : default_ppl(c);
+    int ppl = 1, src = PM_COEF_LDS;
+    if (!std::is_same<T, double>::value) time_tuning(c, p->K, &ppl, &src);
     TimeArgs<T> a{};
     a.coef = coef;
     a.coef_stride = cstride;
@@ -214,7 +245,7 @@ int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
     } else {
         // metadata: np[n_u] seed[n_u] task_off[n_u+1] chunk_off[n_u+1]
         const size_t nmeta = (size_t)4 * n_u + 2;
-        if (c->meta_pending) {
+        if (c->meta_pending && !c->capturing) {
             if (hipEventSynchronize(c->meta_ev) != hipSuccess) return PM_EDEVICE;
             c->meta_pending = false;
         }
@@ -242,8 +273,10 @@ int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
             steps += (double)nps[b] * n_obs * (double)Nt;
         }
         PM_HIP(hipMemcpyAsync(c->meta, h, nmeta * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
-        PM_HIP(hipEventRecord(c->meta_ev, c->stream));
-        c->meta_pending = true;
+        if (!c->capturing) {
+            PM_HIP(hipEventRecord(c->meta_ev, c->stream));
+            c->meta_pending = true;
+        }
         const int64_t *d = (const int64_t *)c->meta;
         a.np_arr = d;
         a.seed_arr = (const uint64_t *)(d + n_u);
@@ -267,11 +300,13 @@ int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
     fa.partials = pa.partials;
 
     if (launch_zero_u64(c->d_queue, 1, c->stream) != hipSuccess) return PM_EDEVICE;
-    PM_HIP(hipEventRecord(c->ev0, c->stream));
-    if (launch_time<T>(a, p->K, ppl, c->src, c->n_cu, c->stream) != hipSuccess) return PM_EDEVICE;
-    PM_HIP(hipEventRecord(c->ev1, c->stream));
-    c->timed = true;
-    c->last_steps = steps;
+    if (!c->capturing) PM_HIP(hipEventRecord(c->ev0, c->stream));
+    if (launch_time<T>(a, p->K, ppl, src, c->n_cu, c->bpc, c->stream) != hipSuccess) return PM_EDEVICE;
+    if (!c->capturing) {
+        PM_HIP(hipEventRecord(c->ev1, c->stream));
+        c->timed = true;
+        c->last_steps = steps;
+    }
     if (launch_time_payoff(pa, c->stream) != hipSuccess) return PM_EDEVICE;
     if (launch_finalize(fa, n_u * n_obs, c->stream) != hipSuccess) return PM_EDEVICE;
     return PM_OK;
@@ -514,9 +549,9 @@ int pm_problem_create(pm_ctx *c, pm_problem **out, int domain, int n_modes, cons
     return PM_OK;
 }
 
-void pm_problem_destroy(pm_problem *p)
+static void problem_release(pm_problem *p)
 {
-    if (!p) return;
+    if (--p->refs > 0) return;
     pm_ctx *c = p->ctx;
     (void)hipSetDevice(c->device);
     // the context's stream may already be gone once the context is closed
@@ -525,6 +560,12 @@ void pm_problem_destroy(pm_problem *p)
     if (p->d_k) (void)hipFree(p->d_k);
     delete p;
     ctx_release(c);
+}
+
+void pm_problem_destroy(pm_problem *p)
+{
+    if (!p) return;
+    problem_release(p);
 }
 
 static int check_time_args(double kappa, double T, double dt)
@@ -685,6 +726,180 @@ int pm_last_kernel_stats(pm_ctx *c, double *ms, double *steps)
     if (hipEventElapsedTime(&f, c->ev0, c->ev1) != hipSuccess) return PM_EDEVICE;
     *ms = f;
     *steps = c->last_steps;
+    return PM_OK;
+}
+
+int pm_set_blocks_per_cu(pm_ctx *c, int bpc)
+{
+    if (!c || c->closed || bpc < 0) return PM_EINVAL;
+    c->bpc = bpc;
+    return PM_OK;
+}
+
+int pm_graph_create_time(pm_ctx *c, const pm_problem *p, int n_u, const double *u,
+                         const int64_t *nps, const uint64_t *seeds, const double *obs, int n_obs,
+                         double kappa, double T, double dt, double *mean, double *var, pm_graph **out)
+{
+    if (!out) return PM_EINVAL;
+    *out = nullptr;
+    if (!ctx_ok(c, p)) return PM_EINVAL;
+    if (p->domain != PM_TORUS || !p->has_theta0) return PM_EINVAL;
+    if (n_u < 1 || !nps || !seeds) return PM_EINVAL;
+    if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(obs) || bad_ptr(mean) || bad_ptr(var)) return PM_EINVAL;
+    if (n_obs < 1) return PM_EINVAL;
+    for (int b = 0; b < n_u; ++b)
+        if (nps[b] < 1 || nps[b] > ((int64_t)1 << 32)) return PM_EINVAL;
+    if (check_time_args(kappa, T, dt)) return PM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+
+    pm_graph *g = new (std::nothrow) pm_graph();
+    if (!g) return PM_ENOMEM;
+    auto fail = [&](int st) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        if (g->priv) {
+            g->priv->d_flags = g->priv_flags;
+            pm_destroy(g->priv);
+        }
+        if (g->cap) (void)hipStreamDestroy(g->cap);
+        delete g;
+        return st;
+    };
+    if (hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) != hipSuccess) return fail(PM_EDEVICE);
+    int st = pm_create(&g->priv, c->device, g->cap);
+    if (st) return fail(st);
+    pm_ctx *q = g->priv;
+    q->ppl = c->ppl;
+    q->src = c->src;
+    q->bpc = c->bpc;
+    for (int k = 0; k <= PM_MAX_K; ++k) {
+        q->tune_ppl[k] = c->tune_ppl[k];
+        q->tune_src[k] = c->tune_src[k];
+    }
+    // graph kernels report through the owner's flags (read by pm_sync(owner))
+    g->priv_flags = q->d_flags;
+    q->d_flags = c->d_flags;
+    auto run = [&]() -> int {
+        return p->prec == PM_FP64
+                   ? observe_time_impl<double>(q, p, n_u, u, nps, seeds, obs, n_obs, kappa, T, dt, mean, var, nullptr)
+                   : observe_time_impl<float>(q, p, n_u, u, nps, seeds, obs, n_obs, kappa, T, dt, mean, var, nullptr);
+    };
+    // eager pass sizes the private workspace, so the capture allocates nothing
+    if ((st = run())) return fail(st);
+    if (hipStreamSynchronize(g->cap) != hipSuccess) return fail(PM_EDEVICE);
+    g->steps = q->last_steps;
+    q->capturing = true;
+    if (hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        q->capturing = false;
+        return fail(PM_EDEVICE);
+    }
+    st = run();
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(g->cap, &graph);
+    q->capturing = false;
+    g->graph = graph;
+    if (st) return fail(st);
+    if (ec != hipSuccess || !graph) return fail(PM_EDEVICE);
+    if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) return fail(PM_EDEVICE);
+    g->owner = c;
+    c->refs++;
+    g->prob = const_cast<pm_problem *>(p);
+    g->prob->refs++;
+    *out = g;
+    return PM_OK;
+}
+
+int pm_graph_launch(pm_graph *g)
+{
+    if (!g || g->owner->closed) return PM_EINVAL;
+    if (hipSetDevice(g->owner->device) != hipSuccess) return PM_EDEVICE;
+    return hipGraphLaunch(g->exec, g->owner->stream) == hipSuccess ? PM_OK : PM_EDEVICE;
+}
+
+int pm_graph_particle_steps(const pm_graph *g, double *steps)
+{
+    if (!g || !steps) return PM_EINVAL;
+    *steps = g->steps;
+    return PM_OK;
+}
+
+void pm_graph_destroy(pm_graph *g)
+{
+    if (!g) return;
+    pm_ctx *c = g->owner;
+    (void)hipSetDevice(c->device);
+    if (!c->closed) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    g->priv->d_flags = g->priv_flags;
+    pm_destroy(g->priv);
+    (void)hipStreamDestroy(g->cap);
+    problem_release(g->prob);
+    ctx_release(c);
+    delete g;
+}
+
+int pm_autotune_time(pm_ctx *c, const pm_problem *p, const double *u, const double *obs, int n_obs,
+                     double kappa, double dt, int64_t np, uint64_t seed, int n_probe_steps,
+                     int *ppl_out, int *src_out, double *ms_out)
+{
+    if (!ctx_ok(c, p)) return PM_EINVAL;
+    if (p->domain != PM_TORUS || !p->has_theta0) return PM_EINVAL;
+    if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(obs) || n_obs < 1) return PM_EINVAL;
+    if (np < 1 || np > ((int64_t)1 << 32) || n_probe_steps < 1) return PM_EINVAL;
+    if (!(std::isfinite(kappa) && kappa >= 0.0) || !finite_pos(dt)) return PM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    if (p->prec == PM_FP64) {  // one compiled variant
+        if (ppl_out) *ppl_out = 1;
+        if (src_out) *src_out = PM_COEF_LDS;
+        if (ms_out) *ms_out = 0.0;
+        return PM_OK;
+    }
+    double *tmp = nullptr;
+    if (hipMalloc((void **)&tmp, 2 * (size_t)n_obs * sizeof(double)) != hipSuccess) return PM_ENOMEM;
+    const int save_ppl = c->ppl, save_src = c->src;
+    const double T = n_probe_steps * dt;
+    int best_ppl = 2, best_src = PM_COEF_LDS;
+    double best = 1e300;
+    int st = PM_OK;
+    const int ppls[3] = {1, 2, 4};
+    for (int src = 0; src < 2 && st == PM_OK; ++src) {
+        for (int pi = 0; pi < 3 && st == PM_OK; ++pi) {
+            c->ppl = ppls[pi];
+            c->src = src;
+            double ms_best = 1e300;
+            for (int rep = 0; rep < 2 && st == PM_OK; ++rep) {
+                st = observe_time_impl<float>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, T, dt, tmp,
+                                              tmp + n_obs, nullptr);
+                if (st) break;
+                if (hipStreamSynchronize(c->stream) != hipSuccess) {
+                    st = PM_EDEVICE;
+                    break;
+                }
+                float f = 0.f;
+                if (hipEventElapsedTime(&f, c->ev0, c->ev1) != hipSuccess) {
+                    st = PM_EDEVICE;
+                    break;
+                }
+                if (f < ms_best) ms_best = f;
+            }
+            if (st == PM_OK && ms_best < best) {
+                best = ms_best;
+                best_ppl = ppls[pi];
+                best_src = src;
+            }
+        }
+    }
+    c->ppl = save_ppl;
+    c->src = save_src;
+    (void)hipFree(tmp);
+    if (st) return st;
+    c->tune_ppl[p->K] = best_ppl;
+    c->tune_src[p->K] = best_src;
+    if (ppl_out) *ppl_out = best_ppl;
+    if (src_out) *src_out = best_src;
+    if (ms_out) *ms_out = best;
     return PM_OK;
 }
 

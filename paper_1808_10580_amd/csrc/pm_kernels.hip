@@ -675,13 +675,14 @@ template hipError_t launch_fold<float>(const FoldArgs &, float *, int, hipStream
 template hipError_t launch_fold<double>(const FoldArgs &, double *, int, hipStream_t);
 
 template <typename T, int K, int PPL, bool SC>
-static hipError_t launch_time_k(const TimeArgs<T> &a, int n_cu, hipStream_t st)
+static hipError_t launch_time_k(const TimeArgs<T> &a, int n_cu, int bpc, hipStream_t st)
 {
     auto kern = k_time<T, K, PPL, SC>;
     int per_cu = 0;
     hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
     if (err != hipSuccess) return err;
     if (per_cu < 1) per_cu = 1;
+    if (bpc > 0 && bpc < per_cu) per_cu = bpc;
     int64_t blocks = (int64_t)per_cu * n_cu;
     const int64_t need = (a.n_tasks + 3) / 4;
     if (blocks > need) blocks = need;
@@ -691,26 +692,26 @@ static hipError_t launch_time_k(const TimeArgs<T> &a, int n_cu, hipStream_t st)
 }
 
 template <typename T>
-hipError_t launch_time(const TimeArgs<T> &a, int K, int ppl, int src, int n_cu, hipStream_t st)
+hipError_t launch_time(const TimeArgs<T> &a, int K, int ppl, int src, int n_cu, int bpc, hipStream_t st)
 {
     return dispatch_k(K, [&](auto kc) -> hipError_t {
         constexpr int KK = decltype(kc)::value;
         if constexpr (std::is_same<T, double>::value) {
-            return launch_time_k<T, KK, 1, false>(a, n_cu, st);
+            return launch_time_k<T, KK, 1, false>(a, n_cu, bpc, st);
         } else {
             if (src == PM_COEF_SCALAR) {
-                if (ppl == 1) return launch_time_k<T, KK, 1, true>(a, n_cu, st);
-                if (ppl == 4) return launch_time_k<T, KK, 4, true>(a, n_cu, st);
-                return launch_time_k<T, KK, 2, true>(a, n_cu, st);
+                if (ppl == 1) return launch_time_k<T, KK, 1, true>(a, n_cu, bpc, st);
+                if (ppl == 4) return launch_time_k<T, KK, 4, true>(a, n_cu, bpc, st);
+                return launch_time_k<T, KK, 2, true>(a, n_cu, bpc, st);
             }
-            if (ppl == 1) return launch_time_k<T, KK, 1, false>(a, n_cu, st);
-            if (ppl == 4) return launch_time_k<T, KK, 4, false>(a, n_cu, st);
-            return launch_time_k<T, KK, 2, false>(a, n_cu, st);
+            if (ppl == 1) return launch_time_k<T, KK, 1, false>(a, n_cu, bpc, st);
+            if (ppl == 4) return launch_time_k<T, KK, 4, false>(a, n_cu, bpc, st);
+            return launch_time_k<T, KK, 2, false>(a, n_cu, bpc, st);
         }
     });
 }
-template hipError_t launch_time<float>(const TimeArgs<float> &, int, int, int, int, hipStream_t);
-template hipError_t launch_time<double>(const TimeArgs<double> &, int, int, int, int, hipStream_t);
+template hipError_t launch_time<float>(const TimeArgs<float> &, int, int, int, int, int, hipStream_t);
+template hipError_t launch_time<double>(const TimeArgs<double> &, int, int, int, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int n_cu, hipStream_t st)
