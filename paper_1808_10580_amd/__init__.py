@@ -47,6 +47,8 @@ def release_all():
     for c in list(_LIVE_CONTEXTS):
         for g in list(getattr(c, "_graphs", ())):
             g.close()
+        for m in list(getattr(c, "_mlps", ())):
+            m.close()
     for p in list(_LIVE_PROBLEMS):
         p.close()
     for c in list(_LIVE_CONTEXTS):
@@ -94,6 +96,17 @@ def _declare(L):
     L.pm_graph_particle_steps.argtypes = [_vp, C.POINTER(_d)]
     L.pm_graph_destroy.argtypes = [_vp]
     L.pm_graph_destroy.restype = None
+    L.pm_mlp_create.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _u64, C.POINTER(_vp)]
+    L.pm_mlp_destroy.argtypes = [_vp]
+    L.pm_mlp_destroy.restype = None
+    L.pm_mlp_n_params.argtypes = [_vp]
+    L.pm_mlp_n_params.restype = C.c_int64
+    L.pm_mlp_set_params.argtypes = [_vp, _vp]
+    L.pm_mlp_get_params.argtypes = [_vp, _vp]
+    L.pm_mlp_set_io.argtypes = [_vp, _vp, _vp, _vp]
+    L.pm_mlp_forward.argtypes = [_vp, _vp, C.c_int, _vp]
+    L.pm_mlp_train_step.argtypes = [_vp, _vp, _vp, C.c_int, C.c_float, _vp]
+    L.pm_mlp_grads.argtypes = [_vp, _vp, _vp, C.c_int, _vp]
     return L
 
 
@@ -156,6 +169,7 @@ class Context:
         self.h = h
         self._problems = weakref.WeakSet()
         self._graphs = weakref.WeakSet()
+        self._mlps = weakref.WeakSet()
         _LIVE_CONTEXTS.add(self)
 
     def bind_stream(self):
@@ -180,10 +194,12 @@ class Context:
         return ms.value, steps.value
 
     def close(self):
-        """Destroy the context; its graphs and problems are destroyed first."""
+        """Destroy the context; its graphs, surrogates and problems first."""
         if getattr(self, "h", None):
             for g in list(getattr(self, "_graphs", ())):
                 g.close()
+            for s in list(getattr(self, "_mlps", ())):
+                s.close()
             for p in list(getattr(self, "_problems", ())):
                 p.close()
             _lib().pm_destroy(self.h)
@@ -397,6 +413,80 @@ class Graph:
     def close(self):
         if getattr(self, "h", None):
             _lib().pm_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """Surrogate MLP on the GPU (include/pm_mlp.h): BF16 MFMA GEMMs with FP32
+    accumulation, FP32 master weights and Adam."""
+
+    def __init__(self, ctx: Context, d_in: int, d_hidden: int, n_hidden: int, d_out: int, max_batch: int,
+                 seed: int = 0):
+        h = C.c_void_p()
+        _check(_lib().pm_mlp_create(ctx.h, d_in, d_hidden, n_hidden, d_out, max_batch, int(seed), C.byref(h)),
+               "pm_mlp_create")
+        self.h, self.ctx = h, ctx
+        self.dims = (d_in, d_hidden, n_hidden, d_out)
+        self.max_batch = max_batch
+        self.n_params = int(_lib().pm_mlp_n_params(h))
+        torch = _torch()
+        self._loss = torch.zeros(1, dtype=torch.float32, device=ctx.device)
+        ctx._mlps.add(self)
+
+    def _f32(self, x):
+        torch = _torch()
+        return _dev(x, torch.float32, self.ctx.device)
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        assert p.size == self.n_params
+        _check(_lib().pm_mlp_set_params(self.h, C.c_void_p(p.ctypes.data)), "pm_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(self.n_params, dtype=np.float32)
+        _check(_lib().pm_mlp_get_params(self.h, C.c_void_p(p.ctypes.data)), "pm_mlp_get_params")
+        return p
+
+    def set_io(self, in_scale=None, out_mean=None, out_std=None):
+        arrs = [None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+                for a in (in_scale, out_mean, out_std)]
+        ptrs = [None if a is None else C.c_void_p(a.ctypes.data) for a in arrs]
+        _check(_lib().pm_mlp_set_io(self.h, *ptrs), "pm_mlp_set_io")
+
+    def forward(self, x):
+        torch = _torch()
+        self.ctx.bind_stream()
+        xt = self._f32(x).reshape(-1, self.dims[0])
+        y = torch.empty((xt.shape[0], self.dims[3]), dtype=torch.float32, device=self.ctx.device)
+        _check(_lib().pm_mlp_forward(self.h, _ptr(xt), xt.shape[0], _ptr(y)), "pm_mlp_forward")
+        return y
+
+    def train_step(self, x, t, lr: float):
+        self.ctx.bind_stream()
+        xt = self._f32(x).reshape(-1, self.dims[0])
+        tt = self._f32(t).reshape(-1, self.dims[3])
+        _check(_lib().pm_mlp_train_step(self.h, _ptr(xt), _ptr(tt), xt.shape[0], float(lr), _ptr(self._loss)),
+               "pm_mlp_train_step")
+        return self._loss
+
+    def grads(self, x, t) -> np.ndarray:
+        self.ctx.bind_stream()
+        xt = self._f32(x).reshape(-1, self.dims[0])
+        tt = self._f32(t).reshape(-1, self.dims[3])
+        g = np.zeros(self.n_params, dtype=np.float32)
+        _check(_lib().pm_mlp_grads(self.h, _ptr(xt), _ptr(tt), xt.shape[0], C.c_void_p(g.ctypes.data)),
+               "pm_mlp_grads")
+        return g
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib().pm_mlp_destroy(self.h)
             self.h = None
 
     def __del__(self):

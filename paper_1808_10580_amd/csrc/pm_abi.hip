@@ -416,6 +416,14 @@ bool ctx_ok(const pm_ctx *c, const pm_problem *p) { return c && p && p->ctx == c
 
 }  // namespace
 
+namespace pm {
+int ctx_device(const pm_ctx *c) { return c->device; }
+hipStream_t ctx_stream(const pm_ctx *c) { return c->stream; }
+bool ctx_closed(const pm_ctx *c) { return c->closed; }
+void ctx_retain(pm_ctx *c) { c->refs++; }
+void ctx_drop(pm_ctx *c) { ctx_release(c); }
+}  // namespace pm
+
 extern "C" {
 
 const char *pm_strerror(int s)

@@ -121,6 +121,17 @@ struct StepArgs {
 
 int row_stride(int domain, int K);
 
+}  // namespace pm
+
+struct pm_ctx;
+namespace pm {
+// Context accessors for other parts of the library (defined in pm_abi.hip).
+int ctx_device(const pm_ctx *c);
+hipStream_t ctx_stream(const pm_ctx *c);
+bool ctx_closed(const pm_ctx *c);
+void ctx_retain(pm_ctx *c);
+void ctx_drop(pm_ctx *c);
+
 template <typename T>
 hipError_t launch_fold(const FoldArgs &a, T *coef, int n_sets, hipStream_t st);
 template <typename T>

@@ -1,0 +1,83 @@
+"""Learned surrogate of the forward map G(u) (first stage of delayed-acceptance pCN).
+
+Training pairs (u, G(u)) come from the particle map itself: u drawn from the
+prior, G evaluated with the batched persistent kernel (pm_observe_time_batch)
+at a reduced particle count.  The network (include/pm_mlp.h) sees whitened
+inputs u / prior_std and standardised outputs; its training and inference run
+on the GPU through libpm's BF16 MFMA kernels.
+"""
+from __future__ import annotations
+
+import math
+import time
+from typing import Dict, Optional
+
+import numpy as np
+
+import paper_1808_10580_amd as pm
+
+
+def particle_dataset(problem, wl, U: np.ndarray, n_particles: int, seed: int, chunk: int = 512) -> np.ndarray:
+    """G(u) for every row of U with the batched particle map (common random
+    numbers: one Philox seed for every evaluation)."""
+    out = []
+    for s in range(0, U.shape[0], chunk):
+        Ub = U[s:s + chunk]
+        nb = Ub.shape[0]
+        m, _ = problem.observe_time_batch(Ub, [n_particles] * nb, [seed] * nb, wl.obs, wl.kappa, wl.T, wl.dt)
+        out.append(m.cpu().numpy())
+    problem.ctx.sync(raise_on_flags=True)
+    return np.concatenate(out, axis=0)
+
+
+class Surrogate:
+    def __init__(self, ctx: pm.Context, prior_std: np.ndarray, d_out: int, d_hidden: int = 512,
+                 n_hidden: int = 3, max_batch: int = 1024, seed: int = 0):
+        self.d_in = int(prior_std.size)
+        self.d_out = d_out
+        self.net = pm.MLP(ctx, self.d_in, d_hidden, n_hidden, d_out, max_batch, seed)
+        self.net.set_io(in_scale=1.0 / np.asarray(prior_std, dtype=np.float64))
+        self.max_batch = max_batch
+
+    def fit(self, U: np.ndarray, G: np.ndarray, epochs: int = 20, batch: int = 1024, lr: float = 1e-3,
+            holdout: float = 0.1, seed: int = 0) -> Dict:
+        import torch
+        rng = np.random.default_rng(seed)
+        n = U.shape[0]
+        idx = rng.permutation(n)
+        n_val = max(1, int(round(holdout * n)))
+        val, tr = idx[:n_val], idx[n_val:]
+        mu = G[tr].mean(axis=0)
+        sd = G[tr].std(axis=0) + 1e-12
+        self.net.set_io(out_mean=mu, out_std=sd)
+        dev = self.net.ctx.device
+        Ut = torch.tensor(U[tr], dtype=torch.float32, device=dev)
+        Gt = torch.tensor(G[tr], dtype=torch.float32, device=dev)
+        hist = {"train": [], "val_rmse": [], "seconds": 0.0, "steps": 0}
+        t0 = time.perf_counter()
+        b = min(batch, self.max_batch)
+        for ep in range(epochs):
+            perm = torch.randperm(Ut.shape[0], device=dev)
+            losses = []
+            for s in range(0, Ut.shape[0] - b + 1, b):
+                sel = perm[s:s + b]
+                loss = self.net.train_step(Ut[sel], Gt[sel], lr)
+                losses.append(loss.clone())
+                hist["steps"] += 1
+            hist["train"].append(float(torch.stack(losses).mean().item()) if losses else float("nan"))
+            pv = self.predict(U[val])
+            hist["val_rmse"].append(float(np.sqrt(np.mean(((pv - G[val]) / sd) ** 2))))
+        torch.cuda.synchronize()
+        hist["seconds"] = time.perf_counter() - t0
+        hist["val_idx"] = val
+        return hist
+
+    def predict(self, U: np.ndarray) -> np.ndarray:
+        U = np.atleast_2d(np.asarray(U, dtype=np.float64))
+        out = []
+        for s in range(0, U.shape[0], self.max_batch):
+            out.append(self.net.forward(U[s:s + self.max_batch]).cpu().numpy().astype(np.float64))
+        return np.concatenate(out, axis=0)
+
+    def __call__(self, u) -> np.ndarray:
+        return self.predict(np.asarray(u)[None, :])[0]
