@@ -192,6 +192,10 @@ const char *pm_strerror(int status);
  * Every choice gives bitwise identical results. */
 int pm_set_tuning(pm_ctx *ctx, int particles_per_lane, int coef_source);
 
+/* Coefficient source of the Dirichlet walk: 0 = LDS, 1 = scalar cache
+ * (default).  Both give bitwise identical results. */
+int pm_set_dirichlet_source(pm_ctx *ctx, int coef_source);
+
 /* Number of persistent 256-thread blocks per compute unit for the time kernel
  * (0 = as many as occupancy allows). */
 int pm_set_blocks_per_cu(pm_ctx *ctx, int blocks_per_cu);

@@ -88,6 +88,7 @@ def _declare(L):
     L.pm_sync.argtypes = [_vp]
     L.pm_last_kernel_stats.argtypes = [_vp, C.POINTER(_d), C.POINTER(_d)]
     L.pm_set_blocks_per_cu.argtypes = [_vp, C.c_int]
+    L.pm_set_dirichlet_source.argtypes = [_vp, C.c_int]
     L.pm_autotune_time.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _i64, _u64, C.c_int,
                                    C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(_d)]
     L.pm_graph_create_time.argtypes = [_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.c_int, _d, _d, _d,
@@ -178,6 +179,9 @@ class Context:
 
     def set_tuning(self, particles_per_lane: int = 0, coef_source: int = 0):
         _check(_lib().pm_set_tuning(self.h, particles_per_lane, coef_source), "pm_set_tuning")
+
+    def set_dirichlet_source(self, coef_source: int = 1):
+        _check(_lib().pm_set_dirichlet_source(self.h, coef_source), "pm_set_dirichlet_source")
 
     def set_blocks_per_cu(self, blocks_per_cu: int = 0):
         _check(_lib().pm_set_blocks_per_cu(self.h, blocks_per_cu), "pm_set_blocks_per_cu")

@@ -52,6 +52,7 @@ struct pm_ctx {
     int ppl = 0;  // explicit tuning (0 = autotuned or default)
     int src = 0;
     int bpc = 0;  // persistent blocks per CU (0 = occupancy limit)
+    int dir_src = PM_COEF_SCALAR;  // Dirichlet kernel coefficient source
     int tune_ppl[PM_MAX_K + 1] = {0};  // autotuned choice per harmonic count K
     int tune_src[PM_MAX_K + 1] = {0};
     bool capturing = false;  // recording a graph: no timing events, no host waits
@@ -369,7 +370,7 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
 
     if (launch_zero_u64(c->d_queue, 1, c->stream) != hipSuccess) return PM_EDEVICE;
     PM_HIP(hipEventRecord(c->ev0, c->stream));
-    if (launch_dirichlet<T>(a, p->K, fk, c->n_cu, c->stream) != hipSuccess) return PM_EDEVICE;
+    if (launch_dirichlet<T>(a, p->K, fk, c->dir_src, c->n_cu, c->stream) != hipSuccess) return PM_EDEVICE;
     PM_HIP(hipEventRecord(c->ev1, c->stream));
     c->timed = true;
     c->last_steps = -1.0;  // counted by the caller from the exit steps
@@ -734,6 +735,13 @@ int pm_last_kernel_stats(pm_ctx *c, double *ms, double *steps)
     if (hipEventElapsedTime(&f, c->ev0, c->ev1) != hipSuccess) return PM_EDEVICE;
     *ms = f;
     *steps = c->last_steps;
+    return PM_OK;
+}
+
+int pm_set_dirichlet_source(pm_ctx *c, int src)
+{
+    if (!c || c->closed || !(src == PM_COEF_LDS || src == PM_COEF_SCALAR)) return PM_EINVAL;
+    c->dir_src = src;
     return PM_OK;
 }
 

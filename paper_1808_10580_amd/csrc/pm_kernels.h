@@ -137,7 +137,7 @@ hipError_t launch_fold(const FoldArgs &a, T *coef, int n_sets, hipStream_t st);
 template <typename T>
 hipError_t launch_time(const TimeArgs<T> &a, int K, int ppl, int src, int n_cu, int bpc, hipStream_t st);
 template <typename T>
-hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int n_cu, hipStream_t st);
+hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_cu, hipStream_t st);
 hipError_t launch_dir_payoff(const DirPayArgs &a, hipStream_t st);
 hipError_t launch_time_payoff(const PayArgs &a, hipStream_t st);
 hipError_t launch_chunk_reduce(const double *vals, int64_t np, int n_obs, double *partials,

@@ -309,16 +309,17 @@ __device__ __forceinline__ double source_at(const FieldArg &f, double x, double 
     else return field_eval(f, x, y);
 }
 
-template <typename T, int K, int FK>
+template <typename T, int K, int FK, bool SC>
 __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
 {
     constexpr int B = Geo<K>::B;
     constexpr int R = Geo<K>::RD;
     constexpr int NC = B * R;
-    __shared__ __align__(16) T lds[NC];
-    for (int e = threadIdx.x; e < NC; e += blockDim.x) lds[e] = a.coef[e];
-    __syncthreads();
-    const T *__restrict__ C = lds;
+    __shared__ __align__(16) T lds[SC ? 4 : NC];
+    if constexpr (!SC) {
+        for (int e = threadIdx.x; e < NC; e += blockDim.x) lds[e] = a.coef[e];
+        __syncthreads();
+    }
 
     const int lane = threadIdx.x & 63;
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
@@ -340,13 +341,18 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
     };
 
     auto substep = [&](T z0, T z1) {
-        __asm__ volatile("" ::: "memory");
         T phx[B], phy[B];
         const T xa = x.at(), ya = y.at();
         trig_basis<T, K>(xa, phx);
         trig_basis<T, K>(ya, phy);
         T vx, vy;
-        disk_velocity<T, K>(C, phx, phy, xa, ya, vx, vy);
+        // coefficients re-read every step: scalar cache (SGPR operands) or LDS
+        if constexpr (SC) {
+            disk_velocity<T, K>(opaque_sgpr((cptr<T>)a.coef), phx, phy, xa, ya, vx, vy);
+        } else {
+            __asm__ volatile("" ::: "memory");
+            disk_velocity<T, K>((const T *)lds, phx, phy, xa, ya, vx, vy);
+        }
         Coord<T> nx = x, ny = y;
         nx.advance(vx + a.v0x, z0, a.sc);
         ny.advance(vy + a.v0y, z1, a.sc);
@@ -714,11 +720,12 @@ template hipError_t launch_time<float>(const TimeArgs<float> &, int, int, int, i
 template hipError_t launch_time<double>(const TimeArgs<double> &, int, int, int, int, int, hipStream_t);
 
 template <typename T>
-hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int n_cu, hipStream_t st)
+hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_cu, hipStream_t st)
 {
     return dispatch_k(K, [&](auto kc) -> hipError_t {
         constexpr int KK = decltype(kc)::value;
-        auto kern = fk == 0 ? k_dirichlet<T, KK, 0> : k_dirichlet<T, KK, 1>;
+        auto kern = src == PM_COEF_SCALAR ? (fk == 0 ? k_dirichlet<T, KK, 0, true> : k_dirichlet<T, KK, 1, true>)
+                                          : (fk == 0 ? k_dirichlet<T, KK, 0, false> : k_dirichlet<T, KK, 1, false>);
         int per_cu = 0;
         hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
         if (err != hipSuccess) return err;
@@ -731,8 +738,8 @@ hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int n_cu, hipStr
         return hipGetLastError();
     });
 }
-template hipError_t launch_dirichlet<float>(const DirArgs<float> &, int, int, int, hipStream_t);
-template hipError_t launch_dirichlet<double>(const DirArgs<double> &, int, int, int, hipStream_t);
+template hipError_t launch_dirichlet<float>(const DirArgs<float> &, int, int, int, int, hipStream_t);
+template hipError_t launch_dirichlet<double>(const DirArgs<double> &, int, int, int, int, hipStream_t);
 
 hipError_t launch_dir_payoff(const DirPayArgs &a, hipStream_t st)
 {

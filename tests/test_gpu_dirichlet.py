@@ -171,3 +171,17 @@ def test_full_size_disk_workload_against_oracle_subsample(pm, ctx, orc):
     se_t = np.sqrt(ref["tau_var"] / 24 + np_(out["tau_var"]) / wl.n_particles)
     zt = np.abs(np_(out["tau_mean"]) - ref["tau_mean"]) / se_t
     assert np.sum(zt > 3) <= 2 and np.all(zt < 4.5), zt
+
+
+def test_coefficient_sources_are_bitwise_identical(pm, ctx):
+    modes, u = _flow()
+    prob = pm.Problem(ctx, "disk", modes, prec="fp32")
+    res = []
+    for src in (0, 1):
+        ctx.set_dirichlet_source(src)
+        out = prob.observe_dirichlet(u, W.fld("const", [-1.0]), W.fld("cos_m_theta", [3]), OBS, 0.25, 1e-3,
+                                     500, 31, 10**6, paths=True)
+        assert ctx.sync() == pm.PM_OK
+        res.append(np_(out["paths"]).copy())
+    ctx.set_dirichlet_source(1)
+    assert np.array_equal(res[0], res[1])
