@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -40,6 +41,8 @@ struct pm_ctx {
     size_t integ_cap = 0;
     void *nsteps = nullptr;
     size_t nsteps_cap = 0;
+    void *order = nullptr;
+    size_t order_cap = 0;
     void *meta = nullptr;
     size_t meta_cap = 0;
     int64_t *h_meta = nullptr;  // pinned staging for batch metadata
@@ -349,9 +352,31 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
         }
     }
 
+    // Deal the walks with the longest expected exit time first: without flow
+    // E tau = (1 - |x|^2) / (4 kappa), so points nearer the centre go first and
+    // the heavy tail of the last walks comes from short-expected points.
+    if ((st = ensure(c, &c->order, &c->order_cap, (size_t)n_obs * sizeof(int)))) return st;
+    {
+        std::vector<double> ho(2 * (size_t)n_obs);
+        if (hipMemcpyAsync(ho.data(), obs, ho.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return PM_EDEVICE;
+        std::vector<int> ord(n_obs);
+        for (int j = 0; j < n_obs; ++j) ord[j] = j;
+        std::stable_sort(ord.begin(), ord.end(), [&](int p, int q) {
+            return ho[2 * p] * ho[2 * p] + ho[2 * p + 1] * ho[2 * p + 1] <
+                   ho[2 * q] * ho[2 * q] + ho[2 * q + 1] * ho[2 * q + 1];
+        });
+        if (hipMemcpyAsync(c->order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice, c->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return PM_EDEVICE;
+    }
+
     DirArgs<T> a{};
     a.coef = coef;
     a.obs = obs;
+    a.order = (const int *)c->order;
     a.n_obs = n_obs;
     a.np = np;
     a.total = total;
@@ -477,7 +502,7 @@ void pm_destroy(pm_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     void *bufs[] = {c->d_flags, c->d_queue, c->coef, c->part, c->part2, c->pay, c->tau, c->capped,
-                    c->meta, c->states, c->exitp, c->integ, c->nsteps};
+                    c->meta, c->states, c->exitp, c->integ, c->nsteps, c->order};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->h_meta) (void)hipHostFree(c->h_meta);

@@ -77,6 +77,7 @@ struct DirArgs {
     double *nsteps;  // [total] steps taken (an exact integer)
     unsigned char *capped;
     unsigned long long *queue;
+    const int *order;  // device [n_obs]: queue position -> observation (longest walks first)
 };
 
 struct DirPayArgs {

@@ -385,9 +385,10 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
                 const int rank = __popcll(m & ((1ull << lane) - 1ull));
                 const int64_t tt = (int64_t)base + rank;
                 if (tt < a.total) {
-                    t = tt;
-                    pj = (uint32_t)(tt / a.np);
-                    pi = (uint32_t)(tt - (int64_t)pj * a.np);
+                    const int64_t jq = tt / a.np;
+                    pj = (uint32_t)a.order[jq];
+                    pi = (uint32_t)(tt - jq * a.np);
+                    t = (int64_t)pj * a.np + pi;
                     x.set(a.obs[2 * pj]);
                     y.set(a.obs[2 * pj + 1]);
                     I = 0.0;

@@ -1,0 +1,131 @@
+"""Plain pCN vs delayed-acceptance pCN with the learned surrogate.
+
+    python -m paper_1808_10580_amd.da_study [--n-train 8192] [--train-particles 2000] [--iters 400]
+
+Setting (the surrogate workload): the main torus problem (168 coefficients,
+49 observation points, T = 1), synthetic data y = G(u*) + N(0, gamma^2),
+gamma = 0.01, with u* a prior draw and G(u*) from the particle map at 1e5
+particles.  Both chains evaluate the particle map with 1e5 particles per point
+(a captured graph replay, common random numbers) to decide acceptance; the
+delayed-acceptance chain screens proposals with the surrogate first.  Both
+start at u* (no burn-in) and use the same pCN step beta, chosen by a short
+pilot of the plain chain for an acceptance rate near 0.25.
+
+Output: one JSON line with samples/s, particle-map calls, acceptance rates and
+the effective sample size (Geyer) of the first 8 coefficients for both chains,
+plus the surrogate's training time and held-out error.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+
+def run(n_train=8192, train_particles=2000, iters=400, pilot=60, chain_particles=100_000, seed=1808,
+        epochs=200, verbose=True):
+    import torch
+
+    import paper_1808_10580_amd as pm
+    import workloads as W
+    from paper_1808_10580_amd import mcmc
+    from paper_1808_10580_amd.surrogate import Surrogate, particle_dataset
+
+    setup = W.surrogate_setup(seed)
+    wl = setup["base"]
+    gamma = setup["gamma"]
+    std = W.prior_std(wl.modes)
+    prior_std = np.concatenate([std, std])
+    ctx = pm.Context(0)
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+    prob.autotune_time(wl.u, wl.obs, wl.kappa, wl.dt, chain_particles, wl.seed, n_probe_steps=50)
+    out = {"n_train": n_train, "train_particles": train_particles, "chain_particles": chain_particles,
+           "iters": iters, "gamma": gamma}
+
+    # data y = G(u*) + gamma eta
+    fwd = mcmc.ParticleForward(prob, wl, chain_particles, wl.seed)
+    g_star = fwd(setup["u_star"])
+    y = g_star + gamma * setup["eta"]
+
+    # training pairs from the prior, evaluated by the batched particle map
+    rng = np.random.default_rng([seed, 6])
+    U = W.draw_prior(wl.modes, rng, n_train)
+    t0 = time.perf_counter()
+    G = particle_dataset(prob, wl, U, train_particles, wl.seed)
+    out["dataset_s"] = time.perf_counter() - t0
+    out["dataset_particle_steps"] = float(n_train) * wl.n_obs * train_particles * wl.n_steps
+    sur = Surrogate(ctx, prior_std, wl.n_obs, seed=seed)
+    hist = sur.fit(U, G, epochs=epochs, batch=1024, lr=1e-3)
+    out["train_s"] = hist["seconds"]
+    out["train_steps"] = hist["steps"]
+    out["val_rmse_standardised"] = hist["val_rmse"][-1]
+    out["val_rmse_G"] = float(np.sqrt(np.mean((sur.predict(U[hist["val_idx"]]) - G[hist["val_idx"]]) ** 2)))
+    out["surrogate_err_at_ustar"] = float(np.sqrt(np.mean((sur(setup["u_star"]) - g_star) ** 2)))
+    if verbose:
+        print(f"[da] dataset {out['dataset_s']:.1f} s, training {out['train_s']:.1f} s, "
+              f"val rmse (std units) {out['val_rmse_standardised']:.3f}", flush=True)
+
+    # pilot: choose beta for plain-pCN acceptance near 0.25
+    beta = 0.02
+    for _ in range(6):
+        c = mcmc.start_chain(setup["u_star"], fwd, y, gamma, seed=seed + 1)
+        mcmc.pcn_steps(c, pilot, fwd, prior_std, y, gamma, beta)
+        acc = c.n_accept / pilot
+        if 0.15 <= acc <= 0.4:
+            break
+        beta *= 2.0 if acc > 0.4 else 0.5
+    out["beta"] = beta
+    out["pilot_accept"] = acc
+
+    coords = list(range(8))
+    res = {}
+    for kind in ("plain", "da"):
+        fwd.calls, fwd.seconds = 0, 0.0
+        sur_calls = [0]
+
+        def surf(u):
+            sur_calls[0] += 1
+            return sur(u)
+
+        c = mcmc.start_chain(setup["u_star"], fwd, y, gamma, seed=seed + 2,
+                             surrogate=surf if kind == "da" else None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if kind == "plain":
+            mcmc.pcn_steps(c, iters, fwd, prior_std, y, gamma, beta)
+        else:
+            mcmc.da_pcn_steps(c, iters, fwd, surf, prior_std, y, gamma, beta)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        S = np.array(c.samples)
+        e = mcmc.ess_min(S, coords)
+        res[kind] = {"seconds": sec, "samples_per_s": iters / sec, "particle_map_calls": c.n_forward,
+                     "accept_rate": c.n_accept / iters, "stage1_pass_rate": c.n_stage1 / iters,
+                     "ess_min_first8": e, "ess_per_s": e / sec,
+                     "surrogate_calls": sur_calls[0]}
+        if verbose:
+            print(f"[da] {kind}: {res[kind]}", flush=True)
+    out["plain"], out["da"] = res["plain"], res["da"]
+    out["speedup_samples_per_s"] = res["da"]["samples_per_s"] / res["plain"]["samples_per_s"]
+    out["speedup_ess_per_s"] = (res["da"]["ess_per_s"] / res["plain"]["ess_per_s"]
+                                if res["plain"]["ess_per_s"] > 0 else None)
+    prob.close()
+    ctx.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n-train", type=int, default=8192)
+    ap.add_argument("--train-particles", type=int, default=2000)
+    ap.add_argument("--iters", type=int, default=400)
+    ap.add_argument("--epochs", type=int, default=200)
+    a = ap.parse_args()
+    print(json.dumps(run(a.n_train, a.train_particles, a.iters, epochs=a.epochs)))
+
+
+if __name__ == "__main__":
+    main()
