@@ -29,6 +29,25 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP/clk/CU
 
+# HBM bytes per launch of the time kernel on this workload, from rocprofv3's
+# FETCH_SIZE and WRITE_SIZE counters scaled by what they read for a plain copy
+# of known size (the copy kernel reads FETCH_SIZE at 0.5 and WRITE_SIZE at 1.0
+# of the bytes moved).  Valid only for the kernel sources they were taken on:
+# reported when the sources still hash to KERNEL_SOURCES_SHA256, else null.
+COUNTER_TRAFFIC_BYTES = None
+KERNEL_SOURCES_SHA256 = None
+KERNEL_SOURCES = ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
+                  "paper_1808_10580_amd/csrc/pm_kernels.hip")
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def flops_per_particle_step(K: int) -> int:
     """Algorithmic FP32 FLOPs of one Euler-Maruyama step of the time kernel
@@ -136,8 +155,12 @@ def main():
     fl = flops_per_particle_step(K)
     kern_s = sum(kernel_ms) / len(kernel_ms) / 1e3
     achieved = fl * steps_per_map / kern_s / 1e12
+    traffic = None
+    if COUNTER_TRAFFIC_BYTES is not None and kernel_sources_sha256() == KERNEL_SOURCES_SHA256:
+        traffic = COUNTER_TRAFFIC_BYTES
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                "traffic_unit": "bytes per launch",
                 "kernel": "k_time<float,6>", "kernel_ms": round(kern_s * 1e3, 3),
                 "flop_per_particle_step": fl,
                 "variant": tuned if tuned else {"particles_per_lane": args.ppl or 2,

@@ -82,6 +82,9 @@ def _declare(L):
                            C.c_uint32, _dp, C.c_int64, _dp]
     L.orc_observe_time.argtypes = [C.POINTER(_Flow), C.POINTER(_Field), _dp, C.c_int, C.c_double,
                                    C.c_double, C.c_double, C.c_int64, C.c_uint64, _dp, _dp]
+    L.orc_observe_time_steps.argtypes = [C.POINTER(_Flow), C.POINTER(_Field), _dp, C.c_int,
+                                         C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_uint64,
+                                         _dp, _dp]
     L.orc_observe_dirichlet.argtypes = [C.POINTER(_Flow), C.POINTER(_Field), C.POINTER(_Field),
                                         _dp, C.c_int, C.c_double, C.c_double, C.c_int64,
                                         C.c_uint64, C.c_int64, _dp, _i64p, _u8p, _dp]
@@ -233,6 +236,35 @@ def observe_time_payoffs(modes, u, theta0, obs, kappa, T, dt, n_particles, seed,
                            int(n_particles), C.c_uint64(int(seed)), _ptr(pay, C.c_double),
                            _ptr(ep, C.c_double) if ep is not None else None)
     return (pay, ep) if endpoints else pay
+
+
+def observe_time_steps_payoffs(modes, u, theta0, obs, kappa, dt, n_steps_, n_particles, seed,
+                               v0=(0.0, 0.0)):
+    """Algorithm 1 with n_steps_ Euler-Maruyama steps of size dt: payoffs
+    theta0(X_{n dt}) [n_obs, Np] (n_steps_ = 0 reads theta0 at the start)."""
+    keep = _Keep()
+    obs = keep.arr(np.asarray(obs, dtype=np.float64).reshape(-1, 2), np.float64)
+    n_obs = obs.shape[0]
+    pay = np.zeros((n_obs, int(n_particles)))
+    fl = _flow(keep, "torus", modes, u, v0)
+    f0 = _field(keep, theta0)
+    lib().orc_observe_time_steps(C.byref(fl), C.byref(f0), _ptr(obs, C.c_double), n_obs, kappa, dt,
+                                 int(n_steps_), int(n_particles), C.c_uint64(int(seed)),
+                                 _ptr(pay, C.c_double), None)
+    return pay
+
+
+def observe_time_multi(modes, u, theta0, obs, kappa, read_steps, dt, n_particles, seed, v0=(0.0, 0.0)):
+    """Observations at several times t_k = read_steps[k] dt: Algorithm 1 run
+    once per (t_k, x_j), each with its own ensemble of n_particles paths of
+    step dt from the same seed.  Returns (mean, var), each [n_read, n_obs]."""
+    ms, vs = [], []
+    for n in read_steps:
+        m, v = mean_var(observe_time_steps_payoffs(modes, u, theta0, obs, kappa, dt, int(n), n_particles,
+                                                   seed, v0))
+        ms.append(m)
+        vs.append(v)
+    return np.array(ms), np.array(vs)
 
 
 def observe_dirichlet_paths(modes, u, f, g, obs, kappa, dt, n_particles, seed, max_steps,

@@ -266,12 +266,25 @@ void orc_path(const orc_flow *fl, double kappa, double dt_eff, uint64_t seed, ui
  * obs[j]; endpoints (nullable) receive X_T.  The loops over (j, i) are
  * independent (Section 3.3) and run under OpenMP.
  */
+void orc_observe_time_steps(const orc_flow *fl, const orc_field *theta0, const double *obs,
+                            int n_obs, double kappa, double dte, int64_t Nt, int64_t Np,
+                            uint64_t seed, double *payoff, double *endpoints);
+
 void orc_observe_time(const orc_flow *fl, const orc_field *theta0, const double *obs,
                       int n_obs, double kappa, double T, double dt, int64_t Np, uint64_t seed,
                       double *payoff, double *endpoints)
 {
     int64_t Nt = orc_n_steps(T, dt);
-    double dte = T / (double)Nt;
+    orc_observe_time_steps(fl, theta0, obs, n_obs, kappa, T / (double)Nt, Nt, Np, seed, payoff,
+                           endpoints);
+}
+
+/* Algorithm 1 with Nt steps of the given size dte (Nt = 0 reads theta0 at the
+   start points). */
+void orc_observe_time_steps(const orc_flow *fl, const orc_field *theta0, const double *obs,
+                            int n_obs, double kappa, double dte, int64_t Nt, int64_t Np,
+                            uint64_t seed, double *payoff, double *endpoints)
+{
     int64_t total = (int64_t)n_obs * Np;
 #pragma omp parallel for schedule(static)
     for (int64_t t = 0; t < total; ++t) {

@@ -1,10 +1,13 @@
 """GPU parity of the surrogate MLP's BF16 MFMA forward and backward kernels
 against the FP64 oracle (oracle/mlp.py).
 
-BF16 rounds every matrix operand to 8 significant bits (relative 2^-9), with
-FP32 accumulation; through four layers of width up to 512 the outputs and
-gradients are expected within a few 1e-3 relative (norm-wise); the tests use
-3e-2 and print the measured errors.
+BF16 rounds every matrix operand to 8 significant bits (unit roundoff
+u = 2^-9), with FP32 accumulation.  Each product therefore carries at most
+about 2u of norm-wise relative error (one rounding per operand), and GELU's
+slope stays within [-0.13, 1.13], so errors add up roughly linearly along the
+chain of products: the forward output is allowed 2u per product (L + 1 of
+them), a gradient 2u per product of the forward and backward chains
+(2 (L + 1)).  The tests print the measured errors (typically 5e-3).
 """
 import numpy as np
 import pytest
@@ -15,6 +18,15 @@ pytestmark = pytest.mark.gpu
 
 FULL = (168, 512, 3, 49)
 TINY = (8, 16, 2, 4)
+U_BF16 = 2.0 ** -9
+
+
+def fwd_tol(dims):
+    return 2 * U_BF16 * (dims[2] + 1)
+
+
+def grad_tol(dims):
+    return 2 * U_BF16 * 2 * (dims[2] + 1)
 
 
 @pytest.fixture(scope="module")
@@ -57,8 +69,8 @@ def test_forward_matches_oracle(pm, ctx, dims, n):
     y = net.forward(x).cpu().numpy()
     ref = orc_mlp.predict(p, dims, x, scale, mu, sd)
     err = _rel(y - mu, ref - mu)
-    print("forward %s n=%d: relative error %.2e" % (dims, n, err))
-    assert err < 3e-2
+    print("forward %s n=%d: relative error %.2e (bound %.2e)" % (dims, n, err, fwd_tol(dims)))
+    assert err < fwd_tol(dims)
     net.close()
 
 
@@ -71,8 +83,8 @@ def test_gradients_match_oracle(pm, ctx, dims, n):
     for l, (K, N) in enumerate(orc_mlp.layer_dims(*dims)):
         for name, size in (("W", K * N), ("b", N)):
             e = _rel(g[off:off + size], ref[off:off + size])
-            print("grad layer %d %s: relative error %.2e" % (l, name, e))
-            assert e < 3e-2
+            print("grad layer %d %s: relative error %.2e (bound %.2e)" % (l, name, e, grad_tol(dims)))
+            assert e < grad_tol(dims)
             off += size
     net.close()
 
@@ -118,5 +130,5 @@ def test_training_fits_a_teacher_network(pm, ctx):
     Xv = rng.standard_normal((512, dims[0]))
     y = net.forward(Xv).cpu().numpy()
     ref = orc_mlp.predict(net.get_params().astype(np.float64), dims, Xv, None, mu, sd)
-    assert _rel(y - mu, ref - mu) < 3e-2
+    assert _rel(y - mu, ref - mu) < fwd_tol(dims)
     net.close()
