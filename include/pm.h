@@ -125,6 +125,27 @@ int pm_observe_time(pm_ctx *ctx, const pm_problem *p, const double *u, const dou
                     int n_obs, double kappa, double T, double dt, int64_t n_particles,
                     uint64_t seed, double *mean, double *var, double *endpoints);
 
+/* Observations at several times along the same paths.  The data of an
+ * inverse problem may observe theta at times t_1 < ... < t_R at each point
+ * (Section 2: observations are pairs (t_j, x_j); Example 3 of Section 4 reads
+ * 13 times at 2 points).  Algorithm 1 run separately per (t_k, x_j) would
+ * launch one ensemble per pair; here one ensemble per point is read out as it
+ * passes each t_k.  With the same seed and step the readout at t_k is path for
+ * path the ensemble Algorithm 1 draws for T = t_k, so each mean has the same
+ * law and standard error; means at different times of one point are
+ * correlated (shared paths).
+ *   read_steps host [n_read], 1 <= n_read <= PM_MAX_READS, strictly
+ *              increasing step counts n_k >= 0; t_k = n_k dt (n_k = 0 reads
+ *              theta0 at x_j)
+ *   dt > 0     the step size (uniform, no rounding to T)
+ *   mean, var  device [n_read][n_obs] FP64
+ * Other arguments as for pm_observe_time.  PM_EINVAL for an empty, too long,
+ * negative or non-increasing read list. */
+#define PM_MAX_READS 64
+int pm_observe_time_multi(pm_ctx *ctx, const pm_problem *p, const double *u, const double *obs_pts,
+                          int n_obs, const int64_t *read_steps, int n_read, double kappa, double dt,
+                          int64_t n_particles, uint64_t seed, double *mean, double *var);
+
 /* Algorithm 2 (Section 3.2, Theorem 3.2) on the unit disk:
  *   payoff_i = theta_dD(X_tau) - int_0^tau f(X_t) dt
  * with the exit detected when |Y|^2 >= 1 after a step (tested in FP64), the
@@ -199,6 +220,12 @@ int pm_set_dirichlet_source(pm_ctx *ctx, int coef_source);
 /* Number of persistent 256-thread blocks per compute unit for the time kernel
  * (0 = as many as occupancy allows). */
 int pm_set_blocks_per_cu(pm_ctx *ctx, int blocks_per_cu);
+
+/* The same for the Dirichlet walk.  Exit times are heavy-tailed, so fewer
+ * resident lanes (each walking more particles from the queue) can finish
+ * sooner than a full chip of lanes with one or two particles each.  Results
+ * do not depend on it. */
+int pm_set_dirichlet_blocks_per_cu(pm_ctx *ctx, int blocks_per_cu);
 
 /* Autotuner for the time kernel (Algorithm 1): times every particles-per-lane
  * and coefficient-source variant on a probe of n_probe_steps steps with the

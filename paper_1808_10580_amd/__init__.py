@@ -78,6 +78,8 @@ def _declare(L):
     L.pm_problem_destroy.argtypes = [_vp]
     L.pm_problem_destroy.restype = None
     L.pm_observe_time.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _d, _i64, _u64, _vp, _vp, _vp]
+    L.pm_observe_time_multi.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp, C.c_int, _d, _d, _i64, _u64,
+                                        _vp, _vp]
     L.pm_observe_time_batch.argtypes = [_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.c_int, _d, _d, _d,
                                         _vp, _vp]
     L.pm_observe_dirichlet.argtypes = [_vp, _vp, _vp, C.POINTER(_Field), C.POINTER(_Field), _vp,
@@ -89,6 +91,7 @@ def _declare(L):
     L.pm_last_kernel_stats.argtypes = [_vp, C.POINTER(_d), C.POINTER(_d)]
     L.pm_set_blocks_per_cu.argtypes = [_vp, C.c_int]
     L.pm_set_dirichlet_source.argtypes = [_vp, C.c_int]
+    L.pm_set_dirichlet_blocks_per_cu.argtypes = [_vp, C.c_int]
     L.pm_autotune_time.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _i64, _u64, C.c_int,
                                    C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(_d)]
     L.pm_graph_create_time.argtypes = [_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.c_int, _d, _d, _d,
@@ -183,6 +186,9 @@ class Context:
     def set_dirichlet_source(self, coef_source: int = 1):
         _check(_lib().pm_set_dirichlet_source(self.h, coef_source), "pm_set_dirichlet_source")
 
+    def set_dirichlet_blocks_per_cu(self, blocks_per_cu: int = 0):
+        _check(_lib().pm_set_dirichlet_blocks_per_cu(self.h, blocks_per_cu), "pm_set_dirichlet_blocks_per_cu")
+
     def set_blocks_per_cu(self, blocks_per_cu: int = 0):
         _check(_lib().pm_set_blocks_per_cu(self.h, blocks_per_cu), "pm_set_blocks_per_cu")
 
@@ -273,6 +279,23 @@ class Problem:
                                     float(dt), int(n_particles), int(seed), _ptr(mean), _ptr(var), _ptr(ep))
         _check(st, "pm_observe_time")
         return (mean, var, ep) if endpoints else (mean, var)
+
+    def observe_time_multi(self, u, obs, kappa, read_steps: Sequence[int], dt, n_particles, seed):
+        """Observations at t_k = read_steps[k] * dt along one ensemble per point:
+        (mean, var) as CUDA float64 tensors [n_read, n_obs]."""
+        torch = _torch()
+        self.ctx.bind_stream()
+        ut = self._u(u)
+        ob = _dev(obs, torch.float64, self.ctx.device).reshape(-1, 2)
+        n_obs = ob.shape[0]
+        rs = np.ascontiguousarray(np.asarray(read_steps, dtype=np.int64).reshape(-1))
+        mean = torch.empty((rs.size, n_obs), dtype=torch.float64, device=self.ctx.device)
+        var = torch.empty_like(mean)
+        st = _lib().pm_observe_time_multi(self.ctx.h, self.h, _ptr(ut), _ptr(ob), n_obs, C.c_void_p(rs.ctypes.data),
+                                          int(rs.size), float(kappa), float(dt), int(n_particles), int(seed),
+                                          _ptr(mean), _ptr(var))
+        _check(st, "pm_observe_time_multi")
+        return mean, var
 
     def observe_time_batch(self, U, n_particles: Sequence[int], seeds: Sequence[int], obs, kappa, T, dt):
         torch = _torch()

@@ -56,6 +56,7 @@ struct pm_ctx {
     int src = 0;
     int bpc = 0;  // persistent blocks per CU (0 = occupancy limit)
     int dir_src = PM_COEF_SCALAR;  // Dirichlet kernel coefficient source
+    int dir_bpc = 0;               // Dirichlet persistent blocks per CU (0 = occupancy)
     int tune_ppl[PM_MAX_K + 1] = {0};  // autotuned choice per harmonic count K
     int tune_src[PM_MAX_K + 1] = {0};
     bool capturing = false;  // recording a graph: no timing events, no host waits
@@ -198,19 +199,25 @@ void time_tuning(const pm_ctx *c, int K, int *ppl, int *src)
 }
 
 template <typename T>
-int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, const int64_t *nps,
-                      const uint64_t *seeds, const double *obs, int n_obs, double kappa, double T_,
-                      double dt, double *mean, double *var, double *endpoints)
+int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, const int64_t *nps,
+                      const uint64_t *seeds, const double *obs, int n_obs, double kappa, double dte,
+                      const int64_t *reads, int n_read, double *mean, double *var, double *endpoints)
 {
-    const int64_t Nt = n_steps_of(T_, dt);
-    const double dte = T_ / (double)Nt;
+    const int64_t Nt = reads[n_read - 1];
     T *coef;
     int64_t cstride;
     int st = fold<T>(c, p, u, n_u, 2 * (int64_t)p->n_modes, &coef, &cstride);
     if (st) return st;
 
     int ppl = 1, src = PM_COEF_LDS;
-    if (!std::is_same<T, double>::value) time_tuning(c, p->K, &ppl, &src);
+    if (!std::is_same<T, double>::value) {
+        if (n_read > 1) {
+            ppl = 2;  // the multi-readout kernel's one FP32 variant
+            src = PM_COEF_SCALAR;
+        } else {
+            time_tuning(c, p->K, &ppl, &src);
+        }
+    }
     TimeArgs<T> a{};
     a.coef = coef;
     a.coef_stride = cstride;
@@ -218,6 +225,8 @@ int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
     a.n_obs = n_obs;
     a.n_u = n_u;
     a.n_steps = Nt;
+    a.n_read = n_read;
+    for (int r = 0; r < n_read; ++r) a.read_at[r] = reads[r];
     a.sc = step_consts<T>(dte, kappa);
     a.v0x = (T)p->v0[0];
     a.v0y = (T)p->v0[1];
@@ -225,12 +234,13 @@ int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
 
     PayArgs pa{};
     pa.n_u = n_u;
+    pa.n_read = n_read;
     pa.theta0 = p->theta0;
     pa.endpoints = endpoints;
     pa.flags = c->d_flags;
 
     FinalArgs fa{};
-    fa.n_obs = n_obs;
+    fa.n_obs = n_obs * n_read;  // n_u == 1 when n_read > 1: rows (r, j)
     fa.mean = mean;
     fa.var = var;
     fa.flags = c->d_flags;
@@ -293,11 +303,12 @@ int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
         pa.chunk_off = a.chunk_off;
         pa.np_arr = a.np_arr;
     }
-    st = ensure(c, &c->part, &c->part_cap, (size_t)total_chunks * 3 * sizeof(double));
+    st = ensure(c, &c->part, &c->part_cap, (size_t)n_read * total_chunks * 3 * sizeof(double));
     if (st) return st;
-    st = ensure(c, &c->states, &c->states_cap, (size_t)total_chunks * 64 * 2 * sizeof(double));
+    st = ensure(c, &c->states, &c->states_cap, (size_t)n_read * total_chunks * 64 * 2 * sizeof(double));
     if (st) return st;
     a.states = (double *)c->states;
+    a.read_stride = total_chunks * 64 * 2;
     pa.states = a.states;
     pa.n_chunks = total_chunks;
     pa.partials = (double *)c->part;
@@ -312,8 +323,19 @@ int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
         c->last_steps = steps;
     }
     if (launch_time_payoff(pa, c->stream) != hipSuccess) return PM_EDEVICE;
-    if (launch_finalize(fa, n_u * n_obs, c->stream) != hipSuccess) return PM_EDEVICE;
+    if (launch_finalize(fa, n_u * n_obs * n_read, c->stream) != hipSuccess) return PM_EDEVICE;
     return PM_OK;
+}
+
+// Single observation time T: N_t = ceil(T/dt) uniform steps of T/N_t.
+template <typename T>
+int observe_time_impl(pm_ctx *c, const pm_problem *p, int n_u, const double *u, const int64_t *nps,
+                      const uint64_t *seeds, const double *obs, int n_obs, double kappa, double T_,
+                      double dt, double *mean, double *var, double *endpoints)
+{
+    const int64_t Nt = n_steps_of(T_, dt);
+    return observe_time_core<T>(c, p, n_u, u, nps, seeds, obs, n_obs, kappa, T_ / (double)Nt, &Nt, 1, mean,
+                                var, endpoints);
 }
 
 template <typename T>
@@ -395,7 +417,8 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
 
     if (launch_zero_u64(c->d_queue, 1, c->stream) != hipSuccess) return PM_EDEVICE;
     PM_HIP(hipEventRecord(c->ev0, c->stream));
-    if (launch_dirichlet<T>(a, p->K, fk, c->dir_src, c->n_cu, c->stream) != hipSuccess) return PM_EDEVICE;
+    if (launch_dirichlet<T>(a, p->K, fk, c->dir_src, c->n_cu, c->dir_bpc, c->stream) != hipSuccess)
+        return PM_EDEVICE;
     PM_HIP(hipEventRecord(c->ev1, c->stream));
     c->timed = true;
     c->last_steps = -1.0;  // counted by the caller from the exit steps
@@ -627,6 +650,27 @@ int pm_observe_time(pm_ctx *c, const pm_problem *p, const double *u, const doubl
     return observe_time_impl<float>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, T, dt, mean, var, endpoints);
 }
 
+int pm_observe_time_multi(pm_ctx *c, const pm_problem *p, const double *u, const double *obs, int n_obs,
+                          const int64_t *reads, int n_read, double kappa, double dt, int64_t np,
+                          uint64_t seed, double *mean, double *var)
+{
+    if (!ctx_ok(c, p)) return PM_EINVAL;
+    if (p->domain != PM_TORUS || !p->has_theta0) return PM_EINVAL;
+    if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(obs) || bad_ptr(mean) || bad_ptr(var)) return PM_EINVAL;
+    if (n_obs < 1) return PM_EINVAL;
+    if (np < 1 || np > ((int64_t)1 << 32)) return PM_EINVAL;
+    if (!reads || n_read < 1 || n_read > PM_MAX_READS) return PM_EINVAL;
+    for (int r = 0; r < n_read; ++r)
+        if (reads[r] < 0 || reads[r] > ((int64_t)1 << 33) || (r > 0 && reads[r] <= reads[r - 1])) return PM_EINVAL;
+    if (!(std::isfinite(kappa) && kappa >= 0.0) || !finite_pos(dt)) return PM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    if (p->prec == PM_FP64)
+        return observe_time_core<double>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, dt, reads, n_read, mean, var,
+                                         nullptr);
+    return observe_time_core<float>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, dt, reads, n_read, mean, var,
+                                    nullptr);
+}
+
 int pm_observe_time_batch(pm_ctx *c, const pm_problem *p, int n_u, const double *u,
                           const int64_t *nps, const uint64_t *seeds, const double *obs, int n_obs,
                           double kappa, double T, double dt, double *mean, double *var)
@@ -767,6 +811,13 @@ int pm_set_dirichlet_source(pm_ctx *c, int src)
 {
     if (!c || c->closed || !(src == PM_COEF_LDS || src == PM_COEF_SCALAR)) return PM_EINVAL;
     c->dir_src = src;
+    return PM_OK;
+}
+
+int pm_set_dirichlet_blocks_per_cu(pm_ctx *c, int bpc)
+{
+    if (!c || c->closed || bpc < 0) return PM_EINVAL;
+    c->dir_bpc = bpc;
     return PM_OK;
 }
 

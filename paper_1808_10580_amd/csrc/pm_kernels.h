@@ -42,13 +42,17 @@ struct TimeArgs {
     int64_t n_steps;
     StepConsts<T> sc;
     T v0x, v0y;
-    double *states;  // [total chunks][64][2] final positions
+    double *states;  // [n_read][total chunks][64][2] positions at each readout
+    int64_t read_stride;  // doubles between readout slots of states
     unsigned long long *queue;
+    int n_read;                      // >= 1; read_at[n_read - 1] == n_steps
+    int64_t read_at[PM_MAX_READS];   // increasing step counts of the readouts
 };
 
 struct PayArgs {
-    const double *states;
-    int64_t n_chunks;
+    const double *states;  // [n_read][n_chunks][64][2]
+    int64_t n_chunks;      // per readout
+    int n_read;
     int n_u;
     int64_t np0;
     const int64_t *np_arr;
@@ -138,7 +142,7 @@ hipError_t launch_fold(const FoldArgs &a, T *coef, int n_sets, hipStream_t st);
 template <typename T>
 hipError_t launch_time(const TimeArgs<T> &a, int K, int ppl, int src, int n_cu, int bpc, hipStream_t st);
 template <typename T>
-hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_cu, hipStream_t st);
+hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_cu, int bpc, hipStream_t st);
 hipError_t launch_dir_payoff(const DirPayArgs &a, hipStream_t st);
 hipError_t launch_time_payoff(const PayArgs &a, hipStream_t st);
 hipError_t launch_chunk_reduce(const double *vals, int64_t np, int n_obs, double *partials,

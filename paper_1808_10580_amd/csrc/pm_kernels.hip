@@ -121,7 +121,7 @@ __device__ __forceinline__ void chunk_stats(bool act, double e, double &cnt, dou
 // map and the reduction tree depend only on (j, i), never on the launch shape,
 // so results are bitwise independent of PPL, grid size and batching.
 // ---------------------------------------------------------------------------
-template <typename T, int K, int PPL, bool SC>
+template <typename T, int K, int PPL, bool SC, bool MT>
 __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
 {
     constexpr int B = Geo<K>::B;
@@ -214,35 +214,83 @@ __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
             }
         };
 
-        int64_t n = 0;
-        for (; n + 1 < a.n_steps; n += 2) {
-            T z0[PPL], z1[PPL], z2[PPL], z3[PPL];
+        if constexpr (!MT) {
+            int64_t n = 0;
+            for (; n + 1 < a.n_steps; n += 2) {
+                T z0[PPL], z1[PPL], z2[PPL], z3[PPL];
 #pragma unroll
-            for (int p = 0; p < PPL; ++p) {
-                const U4 w = philox4x32_10((uint32_t)(n >> 1), pi[p], pj[p], 0u, k0, k1);
-                box_muller(w.x, w.y, z0[p], z1[p]);
-                box_muller(w.z, w.w, z2[p], z3[p]);
+                for (int p = 0; p < PPL; ++p) {
+                    const U4 w = philox4x32_10((uint32_t)(n >> 1), pi[p], pj[p], 0u, k0, k1);
+                    box_muller(w.x, w.y, z0[p], z1[p]);
+                    box_muller(w.z, w.w, z2[p], z3[p]);
+                }
+                step(z0, z1);
+                step(z2, z3);
             }
-            step(z0, z1);
-            step(z2, z3);
-        }
-        if (n < a.n_steps) {
-            T z0[PPL], z1[PPL];
+            if (n < a.n_steps) {
+                T z0[PPL], z1[PPL];
 #pragma unroll
-            for (int p = 0; p < PPL; ++p) {
-                const U4 w = philox4x32_10((uint32_t)(n >> 1), pi[p], pj[p], 0u, k0, k1);
-                box_muller(w.x, w.y, z0[p], z1[p]);
+                for (int p = 0; p < PPL; ++p) {
+                    const U4 w = philox4x32_10((uint32_t)(n >> 1), pi[p], pj[p], 0u, k0, k1);
+                    box_muller(w.x, w.y, z0[p], z1[p]);
+                }
+                step(z0, z1);
             }
-            step(z0, z1);
-        }
 
-        // final states, chunk-major: state[(global chunk) * 64 + lane]
+            // final states, chunk-major: state[(global chunk) * 64 + lane]
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-            if (cval[p]) {
-                double *S = a.states + 2 * ((cb + cix[p]) * 64 + lane);
-                S[0] = x[p].value();
-                S[1] = y[p].value();
+            for (int p = 0; p < PPL; ++p) {
+                if (cval[p]) {
+                    double *S = a.states + 2 * ((cb + cix[p]) * 64 + lane);
+                    S[0] = x[p].value();
+                    S[1] = y[p].value();
+                }
+            }
+        } else {
+            // Several readouts: after the step that completes read_at[r]
+            // steps the positions go to slot r ([r][global chunk][lane]).  The
+            // step count is wave-uniform, so the check is a scalar compare.
+            int r = 0;
+            int64_t next = a.read_at[0];
+            auto readout = [&](int64_t done) {
+                if (done == next) {
+#pragma unroll
+                    for (int p = 0; p < PPL; ++p) {
+                        if (cval[p]) {
+                            double *S = a.states + r * a.read_stride + 2 * ((cb + cix[p]) * 64 + lane);
+                            S[0] = x[p].value();
+                            S[1] = y[p].value();
+                        }
+                    }
+                    ++r;
+                    next = r < a.n_read ? a.read_at[r] : -1;
+                }
+            };
+
+            readout(0);
+            int64_t n = 0;
+            for (; n + 1 < a.n_steps; n += 2) {
+                T z0[PPL], z1[PPL], z2[PPL], z3[PPL];
+#pragma unroll
+                for (int p = 0; p < PPL; ++p) {
+                    const U4 w = philox4x32_10((uint32_t)(n >> 1), pi[p], pj[p], 0u, k0, k1);
+                    box_muller(w.x, w.y, z0[p], z1[p]);
+                    box_muller(w.z, w.w, z2[p], z3[p]);
+                }
+                step(z0, z1);
+                readout(n + 1);
+                step(z2, z3);
+                readout(n + 2);
+            }
+            if (n < a.n_steps) {
+                T z0[PPL], z1[PPL];
+#pragma unroll
+                for (int p = 0; p < PPL; ++p) {
+                    const U4 w = philox4x32_10((uint32_t)(n >> 1), pi[p], pj[p], 0u, k0, k1);
+                    box_muller(w.x, w.y, z0[p], z1[p]);
+                }
+                step(z0, z1);
+                readout(n + 1);
             }
         }
     }
@@ -253,8 +301,9 @@ __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
 __global__ __launch_bounds__(256) void k_time_payoff(const PayArgs a)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (g >= a.n_chunks) return;
+    const int64_t ga = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // readout-major chunk
+    if (ga >= a.n_read * a.n_chunks) return;
+    const int64_t g = ga % a.n_chunks;
     int b = 0;
     int64_t cb = 0, np = a.np0;
     if (a.n_u > 1) {
@@ -273,7 +322,7 @@ __global__ __launch_bounds__(256) void k_time_payoff(const PayArgs a)
     const int64_t j = c / cpo, q = c - j * cpo;
     const int64_t i = q * 64 + lane;
     const bool act = i < np;
-    const double *S = a.states + 2 * (g * 64 + lane);
+    const double *S = a.states + 2 * (ga * 64 + lane);
     const double xd = S[0] - floor(S[0]), yd = S[1] - floor(S[1]);
     double e = 0.0;
     if (act) e = field_eval(a.theta0, xd, yd);
@@ -285,7 +334,7 @@ __global__ __launch_bounds__(256) void k_time_payoff(const PayArgs a)
     double cnt, s, m2;
     chunk_stats(act, e, cnt, s, m2);
     if (lane == 0) {
-        double *P = a.partials + 3 * g;
+        double *P = a.partials + 3 * ga;
         P[0] = cnt;
         P[1] = s;
         P[2] = m2;
@@ -681,10 +730,10 @@ hipError_t launch_fold(const FoldArgs &a, T *coef, int n_sets, hipStream_t st)
 template hipError_t launch_fold<float>(const FoldArgs &, float *, int, hipStream_t);
 template hipError_t launch_fold<double>(const FoldArgs &, double *, int, hipStream_t);
 
-template <typename T, int K, int PPL, bool SC>
+template <typename T, int K, int PPL, bool SC, bool MT = false>
 static hipError_t launch_time_k(const TimeArgs<T> &a, int n_cu, int bpc, hipStream_t st)
 {
-    auto kern = k_time<T, K, PPL, SC>;
+    auto kern = k_time<T, K, PPL, SC, MT>;
     int per_cu = 0;
     hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
     if (err != hipSuccess) return err;
@@ -703,6 +752,11 @@ hipError_t launch_time(const TimeArgs<T> &a, int K, int ppl, int src, int n_cu, 
 {
     return dispatch_k(K, [&](auto kc) -> hipError_t {
         constexpr int KK = decltype(kc)::value;
+        if (a.n_read > 1) {
+            // several readouts: one variant per precision
+            if constexpr (std::is_same<T, double>::value) return launch_time_k<T, KK, 1, false, true>(a, n_cu, bpc, st);
+            else return launch_time_k<T, KK, 2, true, true>(a, n_cu, bpc, st);
+        }
         if constexpr (std::is_same<T, double>::value) {
             return launch_time_k<T, KK, 1, false>(a, n_cu, bpc, st);
         } else {
@@ -721,7 +775,7 @@ template hipError_t launch_time<float>(const TimeArgs<float> &, int, int, int, i
 template hipError_t launch_time<double>(const TimeArgs<double> &, int, int, int, int, int, hipStream_t);
 
 template <typename T>
-hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_cu, hipStream_t st)
+hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_cu, int bpc, hipStream_t st)
 {
     return dispatch_k(K, [&](auto kc) -> hipError_t {
         constexpr int KK = decltype(kc)::value;
@@ -731,6 +785,7 @@ hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_c
         hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
         if (err != hipSuccess) return err;
         if (per_cu < 1) per_cu = 1;
+        if (bpc > 0 && bpc < per_cu) per_cu = bpc;
         int64_t blocks = (int64_t)per_cu * n_cu;
         const int64_t need = (a.total + 255) / 256;
         if (blocks > need) blocks = need;
@@ -739,8 +794,8 @@ hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_c
         return hipGetLastError();
     });
 }
-template hipError_t launch_dirichlet<float>(const DirArgs<float> &, int, int, int, int, hipStream_t);
-template hipError_t launch_dirichlet<double>(const DirArgs<double> &, int, int, int, int, hipStream_t);
+template hipError_t launch_dirichlet<float>(const DirArgs<float> &, int, int, int, int, int, hipStream_t);
+template hipError_t launch_dirichlet<double>(const DirArgs<double> &, int, int, int, int, int, hipStream_t);
 
 hipError_t launch_dir_payoff(const DirPayArgs &a, hipStream_t st)
 {
@@ -751,7 +806,7 @@ hipError_t launch_dir_payoff(const DirPayArgs &a, hipStream_t st)
 
 hipError_t launch_time_payoff(const PayArgs &a, hipStream_t st)
 {
-    const int64_t blocks = (a.n_chunks + 3) / 4;
+    const int64_t blocks = (a.n_read * a.n_chunks + 3) / 4;
     hipLaunchKernelGGL(k_time_payoff, dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
