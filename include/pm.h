@@ -89,8 +89,15 @@ typedef struct {
     const double *params; /* host */
 } pm_field;
 
-/* Largest |k_x|, |k_y| of a wavevector table that the compiled kernels accept. */
+/* Largest |k_x|, |k_y| of a wavevector table for the vector-unit kernels
+ * (every domain and precision). */
 #define PM_MAX_K 8
+/* Torus problems in FP32 accept |k_x|, |k_y| up to PM_MAX_K_MFMA: above
+ * PM_MAX_K the velocity (eq. v_expand as two bilinear forms in the axis
+ * Fourier bases) runs on the matrix cores in split FP16 (hi + lo halves,
+ * three products, FP32 accumulation; about FP32 accuracy).  This is the
+ * regime of Section 4's turbulent example, |k|_2 <= 80 (20,081 modes). */
+#define PM_MAX_K_MFMA 95
 
 /* Create a context on HIP device `device` that enqueues on `stream`
  * (a hipStream_t; NULL = the null stream).  Returns PM_OK, PM_EINVAL or
@@ -104,6 +111,8 @@ int pm_set_stream(pm_ctx *ctx, void *stream);
  *   domain   PM_TORUS (Problem 2.1 on [0,1)^2) or PM_DISK (Problem 2.2 on
  *            the unit disk)
  *   n_modes  M >= 0, k: host [M][2] int32 wavevectors, |k_x|,|k_y| <= PM_MAX_K
+ *            (<= PM_MAX_K_MFMA for PM_TORUS with PM_FP32; then no wavevector
+ *            may be listed twice: PM_EINVAL)
  *   v0       host [2] constant drift added to the Fourier field, or NULL
  *   theta0   host initial condition for pm_observe_time (NULL for PM_DISK)
  *   prec     PM_FP32 or PM_FP64 particle arithmetic
@@ -221,8 +230,8 @@ int pm_set_dirichlet_source(pm_ctx *ctx, int coef_source);
  * (0 = as many as occupancy allows). */
 int pm_set_blocks_per_cu(pm_ctx *ctx, int blocks_per_cu);
 
-/* The same for the Dirichlet walk.  Exit times are heavy-tailed, so fewer
- * resident lanes (each walking more particles from the queue) can finish
+/* The same for the Dirichlet walk (default 2).  Exit times are heavy-tailed,
+ * so fewer resident lanes (each walking more particles from the queue) finish
  * sooner than a full chip of lanes with one or two particles each.  Results
  * do not depend on it. */
 int pm_set_dirichlet_blocks_per_cu(pm_ctx *ctx, int blocks_per_cu);

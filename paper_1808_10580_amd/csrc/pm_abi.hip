@@ -56,7 +56,7 @@ struct pm_ctx {
     int src = 0;
     int bpc = 0;  // persistent blocks per CU (0 = occupancy limit)
     int dir_src = PM_COEF_SCALAR;  // Dirichlet kernel coefficient source
-    int dir_bpc = 0;               // Dirichlet persistent blocks per CU (0 = occupancy)
+    int dir_bpc = 2;               // Dirichlet persistent blocks per CU (0 = occupancy)
     int tune_ppl[PM_MAX_K + 1] = {0};  // autotuned choice per harmonic count K
     int tune_src[PM_MAX_K + 1] = {0};
     bool capturing = false;  // recording a graph: no timing events, no host waits
@@ -89,6 +89,8 @@ struct pm_problem {
     double v0[2] = {0.0, 0.0};
     bool has_theta0 = false;
     FieldArg theta0{};
+    bool hk = false;              // K > PM_MAX_K: matrix-core velocity (torus, FP32)
+    int32_t *d_index = nullptr;   // hk: (k_x, k_y) -> mode index, [(2K+1)^2]
 };
 
 namespace {
@@ -182,6 +184,28 @@ int fold(pm_ctx *c, const pm_problem *p, const double *u, int n_sets, int64_t u_
     return PM_OK;
 }
 
+// Matrix-core coefficient tiles of n_sets parameter sets (high-K torus).
+int fold_hk(pm_ctx *c, const pm_problem *p, const double *u, int n_sets, int64_t u_stride,
+            const unsigned char **out, int64_t *set_bytes)
+{
+    const int64_t sb = hk_set_bytes(p->K);
+    int st = ensure(c, &c->coef, &c->coef_cap, (size_t)n_sets * sb);
+    if (st) return st;
+    HkFoldArgs fa{};
+    fa.index = p->d_index;
+    fa.n_modes = p->n_modes;
+    fa.K = p->K;
+    fa.KT = hk_kt(p->K);
+    fa.NT = hk_nt(p->K);
+    fa.u = u;
+    fa.u_stride = u_stride;
+    fa.set_bytes = sb;
+    if (launch_fold_hk(fa, (unsigned char *)c->coef, n_sets, c->stream) != hipSuccess) return PM_EDEVICE;
+    *out = (const unsigned char *)c->coef;
+    *set_bytes = sb;
+    return PM_OK;
+}
+
 // Particles per lane and coefficient source for the FP32 time kernel:
 // explicit setting, else the autotuned choice for this K, else 2 / LDS.
 void time_tuning(const pm_ctx *c, int K, int *ppl, int *src)
@@ -198,12 +222,136 @@ void time_tuning(const pm_ctx *c, int K, int *ppl, int *src)
     }
 }
 
+// Algorithm 1 with the matrix-core velocity: one task per 64-particle chunk.
+int observe_time_hk(pm_ctx *c, const pm_problem *p, int n_u, const double *u, const int64_t *nps,
+                    const uint64_t *seeds, const double *obs, int n_obs, double kappa, double dte,
+                    const int64_t *reads, int n_read, double *mean, double *var, double *endpoints)
+{
+    const int64_t Nt = reads[n_read - 1];
+    const unsigned char *frag;
+    int64_t sb;
+    int st = fold_hk(c, p, u, n_u, 2 * (int64_t)p->n_modes, &frag, &sb);
+    if (st) return st;
+    HkTimeArgs a{};
+    a.frag = frag;
+    a.set_bytes = sb;
+    a.KT = hk_kt(p->K);
+    a.NT = hk_nt(p->K);
+    a.B = 2 * p->K + 1;
+    a.obs = obs;
+    a.n_obs = n_obs;
+    a.n_u = n_u;
+    a.n_steps = Nt;
+    a.n_read = n_read;
+    for (int r = 0; r < n_read; ++r) a.read_at[r] = reads[r];
+    a.sc = step_consts<float>(dte, kappa);
+    a.v0x = (float)p->v0[0];
+    a.v0y = (float)p->v0[1];
+    a.queue = c->d_queue;
+
+    PayArgs pa{};
+    pa.n_u = n_u;
+    pa.n_read = n_read;
+    pa.theta0 = p->theta0;
+    pa.endpoints = endpoints;
+    pa.flags = c->d_flags;
+    FinalArgs fa{};
+    fa.n_obs = n_obs * n_read;
+    fa.mean = mean;
+    fa.var = var;
+    fa.flags = c->d_flags;
+
+    int64_t total_chunks;
+    double steps = 0.0;
+    if (n_u == 1) {
+        const int64_t cpo = (nps[0] + 63) / 64;
+        total_chunks = cpo * n_obs;
+        a.np0 = nps[0];
+        a.seed0 = seeds[0];
+        a.n_tasks = total_chunks;
+        pa.np0 = nps[0];
+        fa.cpo = cpo;
+        steps = (double)nps[0] * n_obs * (double)Nt;
+    } else {
+        const size_t nmeta = (size_t)4 * n_u + 2;
+        if (c->meta_pending && !c->capturing) {
+            if (hipEventSynchronize(c->meta_ev) != hipSuccess) return PM_EDEVICE;
+            c->meta_pending = false;
+        }
+        if (c->h_meta_cap < nmeta) {
+            if (c->h_meta) (void)hipHostFree(c->h_meta);
+            c->h_meta = nullptr;
+            c->h_meta_cap = 0;
+            if (hipHostMalloc((void **)&c->h_meta, nmeta * sizeof(int64_t)) != hipSuccess) return PM_ENOMEM;
+            c->h_meta_cap = nmeta;
+        }
+        st = ensure(c, &c->meta, &c->meta_cap, nmeta * sizeof(int64_t));
+        if (st) return st;
+        int64_t *h = c->h_meta;
+        int64_t *h_np = h, *h_tk = h + 2 * n_u, *h_ch = h + 3 * n_u + 1;
+        uint64_t *h_sd = (uint64_t *)(h + n_u);
+        h_tk[0] = 0;
+        h_ch[0] = 0;
+        for (int b = 0; b < n_u; ++b) {
+            const int64_t nch = ((nps[b] + 63) / 64) * n_obs;
+            h_np[b] = nps[b];
+            h_sd[b] = seeds[b];
+            h_ch[b + 1] = h_ch[b] + nch;
+            h_tk[b + 1] = h_tk[b] + nch;
+            steps += (double)nps[b] * n_obs * (double)Nt;
+        }
+        PM_HIP(hipMemcpyAsync(c->meta, h, nmeta * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+        if (!c->capturing) {
+            PM_HIP(hipEventRecord(c->meta_ev, c->stream));
+            c->meta_pending = true;
+        }
+        const int64_t *d = (const int64_t *)c->meta;
+        a.np_arr = d;
+        a.seed_arr = (const uint64_t *)(d + n_u);
+        a.task_off = d + 2 * n_u;
+        a.chunk_off = d + 3 * n_u + 1;
+        a.n_tasks = h_tk[n_u];
+        total_chunks = h_ch[n_u];
+        fa.chunk_off = a.chunk_off;
+        fa.np_arr = a.np_arr;
+        pa.chunk_off = a.chunk_off;
+        pa.np_arr = a.np_arr;
+    }
+    st = ensure(c, &c->part, &c->part_cap, (size_t)n_read * total_chunks * 3 * sizeof(double));
+    if (st) return st;
+    st = ensure(c, &c->states, &c->states_cap, (size_t)n_read * total_chunks * 64 * 2 * sizeof(double));
+    if (st) return st;
+    a.states = (double *)c->states;
+    a.read_stride = total_chunks * 64 * 2;
+    pa.states = a.states;
+    pa.n_chunks = total_chunks;
+    pa.partials = (double *)c->part;
+    fa.partials = pa.partials;
+
+    if (launch_zero_u64(c->d_queue, 1, c->stream) != hipSuccess) return PM_EDEVICE;
+    if (!c->capturing) PM_HIP(hipEventRecord(c->ev0, c->stream));
+    if (launch_time_hk(a, c->n_cu, c->stream) != hipSuccess) return PM_EDEVICE;
+    if (!c->capturing) {
+        PM_HIP(hipEventRecord(c->ev1, c->stream));
+        c->timed = true;
+        c->last_steps = steps;
+    }
+    if (launch_time_payoff(pa, c->stream) != hipSuccess) return PM_EDEVICE;
+    if (launch_finalize(fa, n_u * n_obs * n_read, c->stream) != hipSuccess) return PM_EDEVICE;
+    return PM_OK;
+}
+
 template <typename T>
 int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, const int64_t *nps,
                       const uint64_t *seeds, const double *obs, int n_obs, double kappa, double dte,
                       const int64_t *reads, int n_read, double *mean, double *var, double *endpoints)
 {
     const int64_t Nt = reads[n_read - 1];
+    if constexpr (std::is_same<T, float>::value) {
+        if (p->hk)
+            return observe_time_hk(c, p, n_u, u, nps, seeds, obs, n_obs, kappa, dte, reads, n_read, mean, var,
+                                   endpoints);
+    }
     T *coef;
     int64_t cstride;
     int st = fold<T>(c, p, u, n_u, 2 * (int64_t)p->n_modes, &coef, &cstride);
@@ -566,9 +714,21 @@ int pm_problem_create(pm_ctx *c, pm_problem **out, int domain, int n_modes, cons
     for (int m = 0; m < n_modes; ++m) {
         const int ax = k[2 * m] < 0 ? -k[2 * m] : k[2 * m];
         const int ay = k[2 * m + 1] < 0 ? -k[2 * m + 1] : k[2 * m + 1];
-        if (ax > PM_MAX_K || ay > PM_MAX_K) return PM_EUNSUPPORTED;
+        if (ax > PM_MAX_K_MFMA || ay > PM_MAX_K_MFMA) return PM_EUNSUPPORTED;
         if (ax > K) K = ax;
         if (ay > K) K = ay;
+    }
+    const bool hk = K > PM_MAX_K;
+    if (hk && (domain != PM_TORUS || prec != PM_FP32)) return PM_EUNSUPPORTED;
+    std::vector<int32_t> index;
+    if (hk) {
+        const int W = 2 * K + 1;
+        index.assign((size_t)W * W, -1);
+        for (int m = 0; m < n_modes; ++m) {
+            int32_t &slot = index[(size_t)(k[2 * m] + K) * W + (k[2 * m + 1] + K)];
+            if (slot >= 0) return PM_EINVAL;  // a wavevector listed twice
+            slot = m;
+        }
     }
     if (v0 && (!std::isfinite(v0[0]) || !std::isfinite(v0[1]))) return PM_EINVAL;
     FieldArg th{};
@@ -601,6 +761,21 @@ int pm_problem_create(pm_ctx *c, pm_problem **out, int domain, int n_modes, cons
         delete p;
         return PM_EDEVICE;
     }
+    if (hk) {
+        p->hk = true;
+        const size_t ib = index.size() * sizeof(int32_t);
+        if (hipMalloc((void **)&p->d_index, ib) != hipSuccess) {
+            (void)hipFree(p->d_k);
+            delete p;
+            return PM_ENOMEM;
+        }
+        if (hipMemcpy(p->d_index, index.data(), ib, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(p->d_index);
+            (void)hipFree(p->d_k);
+            delete p;
+            return PM_EDEVICE;
+        }
+    }
     c->refs++;
     *out = p;
     return PM_OK;
@@ -615,6 +790,7 @@ static void problem_release(pm_problem *p)
     if (!c->closed) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     if (p->d_k) (void)hipFree(p->d_k);
+    if (p->d_index) (void)hipFree(p->d_index);
     delete p;
     ctx_release(c);
 }
@@ -713,6 +889,34 @@ int pm_observe_dirichlet(pm_ctx *c, const pm_problem *p, const double *u, const 
                                          var, tau_mean, tau_var, n_capped, paths);
 }
 
+// Teacher-forced steps (Y) or velocities (V) through the matrix-core field.
+static int step_hk(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, const double *X,
+                   const uint64_t *n, const uint32_t *i, const uint32_t *j, double kappa, double dt,
+                   uint64_t seed, double *Y, double *V)
+{
+    const unsigned char *frag;
+    int64_t sb;
+    int st = fold_hk(c, p, u, 1, 2 * (int64_t)p->n_modes, &frag, &sb);
+    if (st) return st;
+    HkStepArgs a{};
+    a.frag = frag;
+    a.KT = hk_kt(p->K);
+    a.NT = hk_nt(p->K);
+    a.B = 2 * p->K + 1;
+    a.count = count;
+    a.X = X;
+    a.n = n;
+    a.i = i;
+    a.j = j;
+    a.seed = seed;
+    a.sc = step_consts<float>(dt, kappa);
+    a.v0x = (float)p->v0[0];
+    a.v0y = (float)p->v0[1];
+    a.Y = Y;
+    a.V = V;
+    return launch_step_hk(a, c->stream) == hipSuccess ? PM_OK : PM_EDEVICE;
+}
+
 int pm_step(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, const double *X,
             const uint64_t *n, const uint32_t *i, const uint32_t *j, double kappa, double dt,
             uint64_t seed, double *Y)
@@ -724,6 +928,7 @@ int pm_step(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, cons
         return PM_EINVAL;
     if (!(std::isfinite(kappa) && kappa >= 0.0) || !finite_pos(dt)) return PM_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    if (p->hk) return step_hk(c, p, u, count, X, n, i, j, kappa, dt, seed, Y, nullptr);
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);
         T *coef;
@@ -755,6 +960,7 @@ int pm_velocity(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, 
     if (count == 0) return PM_OK;
     if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(X) || bad_ptr(V)) return PM_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    if (p->hk) return step_hk(c, p, u, count, X, nullptr, nullptr, nullptr, 0.0, 1.0, 0, nullptr, V);
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);
         T *coef;
@@ -942,7 +1148,7 @@ int pm_autotune_time(pm_ctx *c, const pm_problem *p, const double *u, const doub
     if (np < 1 || np > ((int64_t)1 << 32) || n_probe_steps < 1) return PM_EINVAL;
     if (!(std::isfinite(kappa) && kappa >= 0.0) || !finite_pos(dt)) return PM_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
-    if (p->prec == PM_FP64) {  // one compiled variant
+    if (p->prec == PM_FP64 || p->hk) {  // one compiled variant
         if (ppl_out) *ppl_out = 1;
         if (src_out) *src_out = PM_COEF_LDS;
         if (ms_out) *ms_out = 0.0;

@@ -126,6 +126,72 @@ struct StepArgs {
 
 int row_stride(int domain, int K);
 
+// ---------------------------------------------------------------------------
+// High-wavenumber torus path (pm_hk.hip): split-FP16 matrix-core velocity.
+// ---------------------------------------------------------------------------
+constexpr int HK_BASIS_SHIFT = 8;  // the basis enters the products scaled by 2^8
+
+struct HkHeader {        // start of each parameter set's coefficient block
+    float inv_scale;     // 2^-(coefficient shift + HK_BASIS_SHIFT)
+    float cmax;          // max |Cx|, |Cy| (FP32)
+    float pad[62];       // tiles start 256 bytes in
+};
+
+struct HkFoldArgs {
+    const int32_t *index;  // device [(2K+1)^2]: mode of (k_x, k_y) at [(k_x+K)(2K+1) + k_y+K], or -1
+    int n_modes;
+    int K, KT, NT;
+    const double *u;       // device [n_sets][u_stride]
+    int64_t u_stride;
+    int64_t set_bytes;     // bytes per parameter set in the output
+};
+
+struct HkTimeArgs {
+    const unsigned char *frag;  // [n_u][set_bytes]
+    int64_t set_bytes;
+    int KT, NT, B;
+    const double *obs;
+    int n_obs;
+    int n_u;
+    int64_t np0;
+    uint64_t seed0;
+    const int64_t *np_arr;
+    const uint64_t *seed_arr;
+    const int64_t *task_off;   // one task per chunk
+    const int64_t *chunk_off;
+    int64_t n_tasks;
+    int64_t n_steps;
+    StepConsts<float> sc;
+    float v0x, v0y;
+    double *states;            // [n_read][total chunks][64][2]
+    int64_t read_stride;
+    unsigned long long *queue;
+    int n_read;
+    int64_t read_at[PM_MAX_READS];
+};
+
+struct HkStepArgs {
+    const unsigned char *frag;  // one parameter set
+    int KT, NT, B;
+    int64_t count;
+    const double *X;
+    const uint64_t *n;
+    const uint32_t *i;
+    const uint32_t *j;
+    uint64_t seed;
+    StepConsts<float> sc;
+    float v0x, v0y;
+    double *Y;   // step mode
+    double *V;   // velocity mode when non-null (n, i, j, Y unused)
+};
+
+int hk_kt(int K);
+int hk_nt(int K);
+int64_t hk_set_bytes(int K);
+hipError_t launch_fold_hk(const HkFoldArgs &a, unsigned char *out, int n_sets, hipStream_t st);
+hipError_t launch_time_hk(const HkTimeArgs &a, int n_cu, hipStream_t st);
+hipError_t launch_step_hk(const HkStepArgs &a, hipStream_t st);
+
 }  // namespace pm
 
 struct pm_ctx;

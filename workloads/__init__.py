@@ -223,6 +223,32 @@ def batch_main(seed: int = WORKLOAD_SEED, n_u: int = 512, lo: float = 1e3,
                     theta0=base.theta0, extra={"u0": u0, "beta": 0.2})
 
 
+def half_plane(modes: np.ndarray) -> np.ndarray:
+    """One representative of each +-k pair (k_x > 0, or k_x = 0 and k_y > 0); k = 0 dropped."""
+    keep = [(kx, ky) for kx, ky in modes if kx > 0 or (kx == 0 and ky > 0)]
+    return np.asarray(keep, dtype=np.int32).reshape(-1, 2)
+
+
+def turbulent_k80(seed: int = WORKLOAD_SEED, n_particles: int = 100_000) -> Workload:
+    """The regime of the paper's turbulent example: |k|_2 <= 80 (20,081 modes
+    counting k = 0 and both signs; 10,040 half-plane modes, 20,080
+    coefficients), kappa 3e-5, observed at 13 evenly spaced times in [0, 0.5]
+    at (0, 0) and (1/2, 1/2).  The paper does not give theta0 or the prior for
+    it: theta0 is 3 periodised Gaussian bumps (sigma 0.1) and the prior is the
+    |k|^-4 variance of the other workloads.  dt = 1/9600 puts every observation
+    time on the step grid (t_k = 400 k dt, 4,800 steps to T = 0.5).  FP32."""
+    rng = np.random.default_rng([seed, 7])
+    modes = half_plane(l2_ball_modes(80.0))
+    u = draw_prior(modes, rng)
+    theta0 = _gauss_bumps(3, 0.1, rng)
+    obs = np.array([[0.0, 0.0], [0.5, 0.5]])
+    dt = 1.0 / 9600.0
+    reads = (400 * np.arange(13)).astype(np.int64)
+    return Workload("torus-k80-turbulent", "torus", modes, u, obs, kappa=3e-5, dt=dt,
+                    n_particles=n_particles, seed=7, prec="fp32", T=0.5, theta0=theta0,
+                    extra={"read_steps": reads})
+
+
 def surrogate_setup(seed: int = WORKLOAD_SEED) -> dict:
     """Inputs of the delayed-acceptance study: the true parameter u*, the noise level
     and the standard-normal draws that make the synthetic data y = G(u*) + gamma*eta."""
@@ -238,4 +264,5 @@ WORKLOADS = {
     "torus-k6-fp32": time_main,
     "disk-dirichlet": dirichlet_main,
     "torus-k6-batch": batch_main,
+    "torus-k80-turbulent": turbulent_k80,
 }
