@@ -329,8 +329,10 @@ def test_invalid_arguments_raise(pm, ctx):
         with pytest.raises(pm.PMError) as e:
             prob.observe_time(wl.u, wl.obs, kw["kappa"], kw["T"], kw["dt"], kw["n_particles"], 1)
         assert e.value.status == pm.PM_EINVAL
-    with pytest.raises(pm.PMError):
-        pm.Problem(ctx, "torus", np.array([[9, 0]], np.int32), theta0=wl.theta0)
+    with pytest.raises(pm.PMError):  # beyond every compiled path
+        pm.Problem(ctx, "torus", np.array([[96, 0]], np.int32), theta0=wl.theta0)
+    with pytest.raises(pm.PMError):  # FP64 has only the vector path (|k| <= 8)
+        pm.Problem(ctx, "torus", np.array([[9, 0]], np.int32), theta0=wl.theta0, prec="fp64")
     dprob = pm.Problem(ctx, "disk", W.disk_modes())
     with pytest.raises(pm.PMError):
         dprob.observe_time(np.zeros(64), wl.obs, 0.1, 1.0, 0.1, 10, 1)
