@@ -34,8 +34,8 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 # of known size (the copy kernel reads FETCH_SIZE at 0.5 and WRITE_SIZE at 1.0
 # of the bytes moved).  Valid only for the kernel sources they were taken on:
 # reported when the sources still hash to KERNEL_SOURCES_SHA256, else null.
-COUNTER_TRAFFIC_BYTES = None
-KERNEL_SOURCES_SHA256 = None
+COUNTER_TRAFFIC_BYTES = 79_671_072  # FETCH 161.5 KiB x 2 + WRITE 77,480.8 KiB x 1
+KERNEL_SOURCES_SHA256 = "669e917095df8d6a9398fc5ff3898cc3139e7403dd0cb951408223a9a24cd211"
 KERNEL_SOURCES = ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
                   "paper_1808_10580_amd/csrc/pm_kernels.hip")
 
@@ -68,6 +68,28 @@ def flops_per_particle_step(K: int) -> int:
     return basis + contraction + update + bm
 
 
+def flops_per_particle_step_disk(K: int) -> int:
+    """Algorithmic FP32 FLOPs of one step of the Dirichlet walk on the disk:
+    three bilinear forms (psi_F and its two derivatives) over B = 2K+1 basis
+    functions, 3 (B-1) + 3 FMA per row; the trig basis as on the torus; the
+    cutoff (1 - r^2)^2 and its product rule (13); the update and Box-Muller
+    arithmetic as on the torus.  The FP64 exit test and source sum are not
+    counted."""
+    B = 2 * K + 1
+    basis = 2 * (K - 1) * (2 * 1 + 2 * 2)
+    contraction = B * (3 * (B - 1) + 3) * 2
+    return basis + contraction + 13 + 2 * (1 + 2 * 2) + (2 + 4)
+
+
+def flops_per_particle_step_mfma(K: int) -> int:
+    """Split-FP16 matrix-core FLOPs of one step of the high-wavenumber path:
+    two bilinear forms over B = 2K+1 basis functions (2 B^2 multiply-adds) in
+    three FP16 products each (hi hi, hi lo, lo hi).  Padding of the tiles to
+    32 x 16 is not counted."""
+    B = 2 * K + 1
+    return 3 * 2 * B * B * 2
+
+
 def cpu_baseline(wl, n_particles: int):
     import oracle
     oracle.build(force=False)
@@ -79,6 +101,123 @@ def cpu_baseline(wl, n_particles: int):
             "kind": "oracle",
             "sample": f"{wl.n_obs} points x {n_particles} particles x {wl.n_steps} steps "
                       f"({steps:.3g} particle-steps, {dt:.1f} s)"}
+
+
+def _time_steps(run, steps, warmup, ctx):
+    import torch
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    kernel_ms, work = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+        ms, w = ctx.last_kernel_stats()
+        kernel_ms.append(ms)
+        work.append(w)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, kernel_ms, work
+
+
+def bench_other(args):
+    """Secondary workloads (not the default line): the turbulent |k|_2 <= 80
+    problem on the matrix cores, the Dirichlet walk on the disk, and the
+    512-set batch.  Same JSON keys as the main line."""
+    import torch
+    import paper_1808_10580_amd as pm
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    ctx = pm.Context(0)
+    name = args.workload
+    cpu = None
+    if name == "torus-k80-turbulent":
+        wl = W.turbulent_k80()
+        prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+        u = torch.tensor(wl.u, dtype=torch.float64, device=dev)
+        obs = torch.tensor(wl.obs, dtype=torch.float64, device=dev)
+        reads = wl.extra["read_steps"]
+
+        def run():
+            m, _ = prob.observe_time_multi(u, obs, wl.kappa, reads, wl.dt, wl.n_particles, wl.seed)
+            m.cpu()
+            if ctx.sync() != pm.PM_OK:
+                raise pm.PMError(ctx.sync(), "forward map")
+        K = int(abs(wl.modes).max())
+        fl = flops_per_particle_step_mfma(K)
+        rl = {"bound": "mfma", "peak": 2500.0, "unit": "TFLOP/s", "kernel": f"k_time_hk<{(2 * K + 32) // 32}>",
+              "flop_per_particle_step": fl, "dtype_of_peak": "fp16 dense"}
+        desc = ("torus-k80-turbulent: |k|_2<=80 (10,040 modes, 20,080 coefficients), kappa=3e-5, 2 points x 1e5 "
+                "particles, 4,800 steps (dt=1/9600) read out at 13 times in [0, 0.5], FP32 states, split-FP16 "
+                "matrix-core velocity")
+        if not args.no_cpu_baseline:
+            import oracle
+            oracle.build(force=False)
+            n_or, n_st = 256, 400
+            t0 = time.perf_counter()
+            oracle.observe_time(wl.modes, wl.u, wl.theta0, wl.obs, wl.kappa, n_st * wl.dt, wl.dt, n_or, wl.seed)
+            el = time.perf_counter() - t0
+            cpu = {"value": wl.n_obs * n_or * n_st / el, "unit": "particle-steps/s", "cores": oracle.num_threads(),
+                   "kind": "oracle", "sample": f"2 points x {n_or} particles x {n_st} steps ({el:.1f} s)"}
+    elif name == "disk-dirichlet":
+        wl = W.dirichlet_main()
+        prob = pm.Problem(ctx, "disk", wl.modes, prec="fp32")
+        u = torch.tensor(wl.u, dtype=torch.float64, device=dev)
+        obs = torch.tensor(wl.obs, dtype=torch.float64, device=dev)
+        last = {}
+
+        def run():
+            out = prob.observe_dirichlet(u, wl.f, wl.g, obs, wl.kappa, wl.dt, wl.n_particles, wl.seed, wl.max_steps)
+            tau = out["tau_mean"].cpu().numpy()
+            out["mean"].cpu()
+            st = ctx.sync()
+            if st != pm.PM_OK:
+                raise pm.PMError(st, "forward map")
+            last["steps"] = float((tau / wl.dt).sum() * wl.n_particles)
+        K = int(abs(wl.modes).max())
+        fl = flops_per_particle_step_disk(K)
+        rl = {"bound": "alu", "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "kernel": f"k_dirichlet<float,{K}>",
+              "flop_per_particle_step": fl}
+        desc = ("disk-dirichlet: unit disk, 64-coefficient stream function x (1-r^2)^2, kappa=0.02, g=cos 3phi, "
+                "f=-1, 25 points x 5e4 particles, dt=1e-4, walks until exit, FP32 states + FP64 exit test")
+    elif name == "torus-k6-batch":
+        wl = W.batch_main()
+        prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+        U = torch.tensor(wl.u, dtype=torch.float64, device=dev)
+        obs = torch.tensor(wl.obs, dtype=torch.float64, device=dev)
+        prob.autotune_time(U[0], obs, wl.kappa, wl.dt, 100_000, 1, n_probe_steps=100)
+
+        def run():
+            m, _ = prob.observe_time_batch(U, wl.n_particles, wl.seed, obs, wl.kappa, wl.T, wl.dt)
+            m.cpu()
+            if ctx.sync() != pm.PM_OK:
+                raise pm.PMError(ctx.sync(), "forward map")
+        K = int(abs(wl.modes).max())
+        fl = flops_per_particle_step(K)
+        rl = {"bound": "alu", "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "kernel": f"k_time<float,{K}>",
+              "flop_per_particle_step": fl}
+        desc = ("torus-k6-batch: 512 pCN proposals (beta 0.2) of the |k|_inf<=6 problem in one launch, per-set "
+                "particle counts log-uniform in [1e3, 1e5], 49 points, 1000 steps")
+    else:
+        print(f"unknown workload {name}", file=sys.stderr)
+        sys.exit(2)
+
+    elapsed, kernel_ms, work = _time_steps(run, args.steps, args.warmup, ctx)
+    if name == "disk-dirichlet":
+        steps_per_map = last["steps"]
+    else:
+        steps_per_map = work[-1]
+    kern_s = sum(kernel_ms) / len(kernel_ms) / 1e3
+    achieved = fl * steps_per_map / kern_s / 1e12
+    rl.update({"achieved": round(achieved, 3), "frac": round(achieved / rl["peak"], 4), "traffic": None,
+               "kernel_ms": round(kern_s * 1e3, 3)})
+    out = {"metric": "particle-steps/s at 1 GPU", "value": steps_per_map * args.steps / elapsed,
+           "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": desc, "particle_steps_per_step": steps_per_map},
+           "roofline": rl, "cpu_baseline": cpu}
+    print(json.dumps(out))
 
 
 def main():
@@ -96,12 +235,17 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "kernel that calibrates the profiler's FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--workload", default="torus-k6-fp32",
+                    help="torus-k6-fp32 (the benchmark line), torus-k80-turbulent, disk-dirichlet, torus-k6-batch")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the particle map's "
               "multi-GPU sharding is described in DESIGN.md and not built.", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "torus-k6-fp32":
+        bench_other(args)
+        return
 
     import torch
     import paper_1808_10580_amd as pm

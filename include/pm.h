@@ -216,7 +216,7 @@ int pm_last_kernel_stats(pm_ctx *ctx, double *ms, double *particle_steps);
 
 const char *pm_strerror(int status);
 
-/* Kernel tuning knob for the time kernel: particles per lane (1, 2 or 4) and
+/* Kernel tuning knob for the time kernel: particles per lane (1 to 4) and
  * coefficient source (0 = LDS, 1 = scalar cache).  particles_per_lane = 0
  * selects the autotuned choice for the problem's K, else 2 particles per lane.
  * Every choice gives bitwise identical results. */

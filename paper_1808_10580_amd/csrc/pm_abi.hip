@@ -694,7 +694,7 @@ int pm_set_stream(pm_ctx *c, void *stream)
 int pm_set_tuning(pm_ctx *c, int ppl, int src)
 {
     if (!c || c->closed) return PM_EINVAL;
-    if (!(ppl == 0 || ppl == 1 || ppl == 2 || ppl == 4)) return PM_EINVAL;
+    if (!(ppl == 0 || (ppl >= 1 && ppl <= 4))) return PM_EINVAL;
     if (!(src == 0 || src == 1)) return PM_EINVAL;
     c->ppl = ppl;
     c->src = src;
@@ -1161,9 +1161,9 @@ int pm_autotune_time(pm_ctx *c, const pm_problem *p, const double *u, const doub
     int best_ppl = 2, best_src = PM_COEF_LDS;
     double best = 1e300;
     int st = PM_OK;
-    const int ppls[3] = {1, 2, 4};
+    const int ppls[4] = {1, 2, 3, 4};
     for (int src = 0; src < 2 && st == PM_OK; ++src) {
-        for (int pi = 0; pi < 3 && st == PM_OK; ++pi) {
+        for (int pi = 0; pi < 4 && st == PM_OK; ++pi) {
             c->ppl = ppls[pi];
             c->src = src;
             double ms_best = 1e300;

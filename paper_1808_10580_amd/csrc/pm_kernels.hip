@@ -121,11 +121,8 @@ __device__ __forceinline__ void chunk_stats(bool act, double e, double &cnt, dou
 // map and the reduction tree depend only on (j, i), never on the launch shape,
 // so results are bitwise independent of PPL, grid size and batching.
 // ---------------------------------------------------------------------------
-// Four particles per lane need ~186 registers (two waves per SIMD); capping
-// that variant at three waves trades a few spills for latency hiding.
 template <typename T, int K, int PPL, bool SC, bool MT>
-__global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(PPL == 4 && !SC ? 3 : 1, PPL == 4 && !SC ? 3 : 8))) void k_time(const TimeArgs<T> a)
+__global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
 {
     constexpr int B = Geo<K>::B;
     constexpr int R = Geo<K>::RT;
@@ -765,10 +762,12 @@ hipError_t launch_time(const TimeArgs<T> &a, int K, int ppl, int src, int n_cu, 
         } else {
             if (src == PM_COEF_SCALAR) {
                 if (ppl == 1) return launch_time_k<T, KK, 1, true>(a, n_cu, bpc, st);
+                if (ppl == 3) return launch_time_k<T, KK, 3, true>(a, n_cu, bpc, st);
                 if (ppl == 4) return launch_time_k<T, KK, 4, true>(a, n_cu, bpc, st);
                 return launch_time_k<T, KK, 2, true>(a, n_cu, bpc, st);
             }
             if (ppl == 1) return launch_time_k<T, KK, 1, false>(a, n_cu, bpc, st);
+            if (ppl == 3) return launch_time_k<T, KK, 3, false>(a, n_cu, bpc, st);
             if (ppl == 4) return launch_time_k<T, KK, 4, false>(a, n_cu, bpc, st);
             return launch_time_k<T, KK, 2, false>(a, n_cu, bpc, st);
         }

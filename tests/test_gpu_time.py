@@ -274,7 +274,7 @@ def test_bitwise_identical_across_launch_shapes(pm, ctx):
     wl = W.time_main()
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
     res = []
-    for ppl, src in ((1, 0), (2, 0), (4, 0), (1, 1), (2, 1), (4, 1)):
+    for ppl, src in ((1, 0), (2, 0), (3, 0), (4, 0), (1, 1), (2, 1), (3, 1), (4, 1)):
         ctx.set_tuning(ppl, src)
         m, v = prob.observe_time(wl.u, wl.obs, wl.kappa, 0.2, wl.dt, 3000, wl.seed)
         res.append((np_(m), np_(v)))
