@@ -268,7 +268,8 @@ int observe_time_hk(pm_ctx *c, const pm_problem *p, int n_u, const double *u, co
         total_chunks = cpo * n_obs;
         a.np0 = nps[0];
         a.seed0 = seeds[0];
-        a.n_tasks = total_chunks;
+        const int64_t cpt = hk_particles_per_task() / 64;  // chunks per task (one block)
+        a.n_tasks = (total_chunks + cpt - 1) / cpt;
         pa.np0 = nps[0];
         fa.cpo = cpo;
         steps = (double)nps[0] * n_obs * (double)Nt;
@@ -297,7 +298,8 @@ int observe_time_hk(pm_ctx *c, const pm_problem *p, int n_u, const double *u, co
             h_np[b] = nps[b];
             h_sd[b] = seeds[b];
             h_ch[b + 1] = h_ch[b] + nch;
-            h_tk[b + 1] = h_tk[b] + nch;
+            const int64_t cpt = hk_particles_per_task() / 64;
+            h_tk[b + 1] = h_tk[b] + (nch + cpt - 1) / cpt;
             steps += (double)nps[b] * n_obs * (double)Nt;
         }
         PM_HIP(hipMemcpyAsync(c->meta, h, nmeta * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));

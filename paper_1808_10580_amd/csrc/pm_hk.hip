@@ -81,6 +81,8 @@ __device__ void hk_coef(const HkFoldArgs &a, const double *__restrict__ u, int i
 __global__ __launch_bounds__(256) void k_fold_hk(const HkFoldArgs a, unsigned char *__restrict__ out)
 {
     __shared__ float red[256];
+    __shared__ int lim[16];
+    if (threadIdx.x < 16) lim[threadIdx.x] = 0;
     const int s = blockIdx.x;
     const double *__restrict__ u = a.u + (int64_t)s * a.u_stride;
     unsigned char *base = out + (int64_t)s * a.set_bytes;
@@ -134,7 +136,10 @@ __global__ __launch_bounds__(256) void k_fold_hk(const HkFoldArgs a, unsigned ch
         const int64_t frag = ((tile * 4) + 2 * comp) * 64 + lane;  // hi fragment; lo is the next one
         t[frag * 8 + e] = hi;
         t[(frag + 64) * 8 + e] = lo;
+        if (v != 0.f) atomicMax(&lim[nt], kt + 1);
     }
+    __syncthreads();
+    if (threadIdx.x < 16) h->kt_lim[threadIdx.x] = (unsigned char)lim[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -152,100 +157,146 @@ __device__ __forceinline__ float hk_phase(int n, float sh, float sl)
     return f + __builtin_fmaf(fn, sl, e);
 }
 
-// phi_{i0 .. i0+7}(s) for i0 = 8 m: sin 4m (or 1 for m = 0), cos/sin 4m+1 ..
-// 4m+3, cos 4m+4; entries with index >= B are zero.
-__device__ __forceinline__ void hk_basis8(int i0, int B, float sh, float sl, float *o)
+// A lane needs, per particle, runs of D consecutive frequencies n0 + d that
+// repeat every S frequencies (one run per tile).  The first run and the
+// rotation by S come from the hardware sine/cosine; each further run is the
+// previous one rotated by the angle addition theorems,
+//   cos((n+S)t) = cos(nt) cos(St) - sin(nt) sin(St),
+//   sin((n+S)t) = sin(nt) cos(St) + cos(nt) sin(St).
+template <int D>
+struct Run {
+    float c[D], s[D], cS, sS;
+};
+
+template <int D>
+__device__ __forceinline__ void run_init(Run<D> &r, int n0, int S, float sh, float sl)
 {
-    const int m4 = i0 >> 1;  // 4 m
 #pragma unroll
-    for (int d = 0; d <= 4; ++d) {
-        const float ph = hk_phase(m4 + d, sh, sl);
-        float sn, cs;
-        sincos_rev(ph, sn, cs);
-        if (d == 0) o[0] = (i0 == 0) ? 1.f : sn;
-        else if (d == 4) o[7] = cs;
-        else {
-            o[2 * d - 1] = cs;
-            o[2 * d] = sn;
-        }
+    for (int d = 0; d < D; ++d) sincos_rev(hk_phase(n0 + d, sh, sl), r.s[d], r.c[d]);
+    sincos_rev(hk_phase(S, sh, sl), r.sS, r.cS);
+}
+
+template <int D>
+__device__ __forceinline__ void run_next(Run<D> &r)
+{
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const float c = __builtin_fmaf(r.c[d], r.cS, -(r.s[d] * r.sS));
+        const float s = __builtin_fmaf(r.s[d], r.cS, r.c[d] * r.sS);
+        r.c[d] = c;
+        r.s[d] = s;
     }
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-        if (i0 + e >= B) o[e] = 0.f;
-}
-
-// phi_{j0 .. j0+3}(s) for j0 = 4 m: sin 2m (or 1 for m = 0), cos 2m+1, sin 2m+1, cos 2m+2.
-__device__ __forceinline__ void hk_basis4(int j0, int B, float sh, float sl, float *o)
-{
-    const int m2 = j0 >> 1;
-    float s0, c0, s1, c1, s2, c2;
-    sincos_rev(hk_phase(m2, sh, sl), s0, c0);
-    sincos_rev(hk_phase(m2 + 1, sh, sl), s1, c1);
-    sincos_rev(hk_phase(m2 + 2, sh, sl), s2, c2);
-    o[0] = (j0 == 0) ? 1.f : s0;
-    o[1] = c1;
-    o[2] = s1;
-    o[3] = c2;
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-        if (j0 + e >= B) o[e] = 0.f;
 }
 
 // ---------------------------------------------------------------------------
-// Velocity of the particle held by each lane of the wave (all 64 lanes take
-// part; lanes without a particle pass any finite position).
+// Velocity of the particle held by each thread of the block (all 256 threads
+// take part; threads without a particle pass any finite position).  The
+// coefficient tiles of one nt stage (KT x 4 fragments of 1 KB) are staged in
+// LDS, double-buffered: while the matrix cores work on stage nt, the block's
+// loads of stage nt+1 are in flight.
 // ---------------------------------------------------------------------------
-template <int KT>
-__device__ __forceinline__ void hk_velocity(const unsigned char *__restrict__ set, int NT, int B, float xh, float xl,
-                                            float yh, float yl, float &vx, float &vy)
+template <int KT, int RB>
+__device__ __forceinline__ void hk_velocity_block(const unsigned char *__restrict__ set, int NT, int B, float xh,
+                                                  float xl, float yh, float yl, f16x8 *__restrict__ lds, float &vx,
+                                                  float &vy)
 {
-    const int lane = threadIdx.x & 63;
+    constexpr int FR = KT * 4 * 64;  // fragments (f16x8) per nt stage
+    constexpr int PER = FR / 256;    // per thread: KT
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int g = lane >> 4, c = lane & 15;
     const HkHeader *h = reinterpret_cast<const HkHeader *>(set);
     const float inv = h->inv_scale;
     const f16x8 *__restrict__ tiles = reinterpret_cast<const f16x8 *>(set + sizeof(HkHeader));
 
-    // positions of the particles this lane serves in the contraction
-    float pxh[4], pxl[4], pyh[4], pyl[4];
+    // Stage nt of the tiles goes straight from global memory into LDS buffer
+    // buf (global_load_lds: each lane writes 16 bytes at a wave-uniform base
+    // plus 16 x lane).  Fragment tid + 256 q of a stage belongs to tile
+    // kt = q; tiles at or past kt_lim[nt] are zero and are neither loaded nor
+    // used.
+    auto stage_load = [&](int nt_, int buf) {
+        const int lim = h->kt_lim[nt_];
+        const int wv = tid >> 6;
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
+        for (int q = 0; q < PER; ++q) {
+            if (q < lim) {
+                const f16x8 *src = tiles + (int64_t)nt_ * FR + 256 * q + tid;
+                f16x8 *dst = lds + buf * FR + 256 * q + 64 * wv;
+                __builtin_amdgcn_global_load_lds((const void *)src, (__attribute__((address_space(3))) void *)dst, 16,
+                                                 0, 0);
+            }
+        }
+    };
+    stage_load(0, 0);
+
+    // positions of the particles this lane serves in the contraction
+    float pxh[RB], pxl[RB], pyh[RB], pyl[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
         const int src = 16 * rb + c;
         pxh[rb] = __shfl(xh, src);
         pxl[rb] = __shfl(xl, src);
         pyh[rb] = __shfl(yh, src);
         pyl[rb] = __shfl(yl, src);
     }
-    // B operands: phi(x) x 2^8 split into FP16 pairs
-    f16x8 bh[KT][4], bl[KT][4];
+    // B operands: phi_{32 kt + 8 g + e}(x) x 2^8 split into FP16 pairs;
+    // frequencies 16 kt + 4 g + d (d = 0..4)
+    f16x8 bh[KT][RB], bl[KT][RB];
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt) {
+    for (int rb = 0; rb < RB; ++rb) {
+        Run<5> rx;
+        run_init(rx, 4 * g, 16, pxh[rb], pxl[rb]);
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
+        for (int kt = 0; kt < KT; ++kt) {
+            if (kt) run_next(rx);
+            const int i0 = 32 * kt + 8 * g;
             float o[8];
-            hk_basis8(32 * kt + 8 * g, B, pxh[rb], pxl[rb], o);
+            o[0] = (i0 == 0) ? 1.f : rx.s[0];
+            o[1] = rx.c[1];
+            o[2] = rx.s[1];
+            o[3] = rx.c[2];
+            o[4] = rx.s[2];
+            o[5] = rx.c[3];
+            o[6] = rx.s[3];
+            o[7] = rx.c[4];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const float v = o[e] * (float)(1 << HK_BASIS_SHIFT);
+                const float v = (i0 + e < B) ? o[e] * (float)(1 << HK_BASIS_SHIFT) : 0.f;
                 const _Float16 hi = (_Float16)v;
                 bh[kt][rb][e] = hi;
                 bl[kt][rb][e] = (_Float16)(v - (float)hi);
             }
         }
     }
-    float ax[4] = {0.f, 0.f, 0.f, 0.f}, ay[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int nt = 0; nt < NT; ++nt) {
-        f32x4 dx[4], dy[4];
+    // y basis runs: frequencies 8 nt + 2 g + d (d = 0..2), one run per rb
+    Run<3> ry[RB];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
+    for (int rb = 0; rb < RB; ++rb) run_init(ry[rb], 2 * g, 8, pyh[rb], pyl[rb]);
+
+    __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0) expcnt(0) lgkmcnt(0): stage 0 is in LDS
+    __syncthreads();
+
+    float ax[RB], ay[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) ax[rb] = ay[rb] = 0.f;
+    for (int nt = 0; nt < NT; ++nt) {
+        const f16x8 *__restrict__ cur = lds + (nt & 1) * FR;
+        const int lcur = h->kt_lim[nt];
+        // buffer (nt+1)&1 was last read in iteration nt-1, before its barrier
+        if (nt + 1 < NT) stage_load(nt + 1, (nt + 1) & 1);
+        f32x4 dx[RB], dy[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
             dx[rb] = (f32x4){0.f, 0.f, 0.f, 0.f};
             dy[rb] = (f32x4){0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt) {
-            const f16x8 *f = tiles + ((int64_t)(nt * KT + kt) * 4) * 64 + lane;
+            if (kt >= lcur) break;  // zero tiles (uniform)
+            const f16x8 *f = cur + kt * 4 * 64 + lane;
             const f16x8 xhi = f[0], xlo = f[64], yhi = f[128], ylo = f[192];
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
+            for (int rb = 0; rb < RB; ++rb) {
                 dx[rb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xhi, bh[kt][rb], dx[rb], 0, 0, 0);
                 dx[rb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xhi, bl[kt][rb], dx[rb], 0, 0, 0);
                 dx[rb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xlo, bh[kt][rb], dx[rb], 0, 0, 0);
@@ -255,54 +306,67 @@ __device__ __forceinline__ void hk_velocity(const unsigned char *__restrict__ se
             }
         }
         // y form: rows j = 16 nt + 4 g + r of particle 16 rb + c
+        const int j0 = 16 * nt + 4 * g;
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
+        for (int rb = 0; rb < RB; ++rb) {
+            if (nt) run_next(ry[rb]);
             float f4[4];
-            hk_basis4(16 * nt + 4 * g, B, pyh[rb], pyl[rb], f4);
+            f4[0] = (j0 == 0) ? 1.f : ry[rb].s[0];
+            f4[1] = ry[rb].c[1];
+            f4[2] = ry[rb].s[1];
+            f4[3] = ry[rb].c[2];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                ax[rb] = __builtin_fmaf(dx[rb][r], f4[r], ax[rb]);
-                ay[rb] = __builtin_fmaf(dy[rb][r], f4[r], ay[rb]);
+                const float fr = (j0 + r < B) ? f4[r] : 0.f;
+                ax[rb] = __builtin_fmaf(dx[rb][r], fr, ax[rb]);
+                ay[rb] = __builtin_fmaf(dy[rb][r], fr, ay[rb]);
             }
         }
+        __builtin_amdgcn_s_waitcnt(0);  // stage nt+1 has landed in LDS
+        __syncthreads();
     }
     // sum over the four row groups (fixed butterfly: identical in every lane)
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
+    for (int rb = 0; rb < RB; ++rb) {
         ax[rb] += __shfl_xor(ax[rb], 16);
         ay[rb] += __shfl_xor(ay[rb], 16);
         ax[rb] += __shfl_xor(ax[rb], 32);
         ay[rb] += __shfl_xor(ay[rb], 32);
     }
-    // lane l = 16 g + c holds particle l in row block g
+    // lane l = 16 g + c holds particle 16 (g mod RB) + c (with RB = 2 the
+    // upper half of the wave mirrors the lower half)
+    const int rsel = g % RB;
     float sx = ax[0], sy = ay[0];
-    if (g == 1) {
-        sx = ax[1];
-        sy = ay[1];
-    } else if (g == 2) {
-        sx = ax[2];
-        sy = ay[2];
-    } else if (g == 3) {
-        sx = ax[3];
-        sy = ay[3];
-    }
+#pragma unroll
+    for (int rb = 1; rb < RB; ++rb)
+        if (rsel == rb) {
+            sx = ax[rb];
+            sy = ay[rb];
+        }
     vx = sx * inv;
     vy = sy * inv;
 }
 
 // ---------------------------------------------------------------------------
-// Algorithm 1 with the matrix-core velocity, persistent.  A task is one
-// 64-particle chunk of one parameter set (the chunk layout and the reduction
-// of the VALU time kernel), read out at the step counts read_at[].
+// Algorithm 1 with the matrix-core velocity, persistent.  A task is up to 4
+// consecutive 64-particle chunks of one parameter set, one per wave of the
+// block (the chunk layout and the reduction of the VALU time kernel); a wave
+// without a chunk walks a dummy particle so that the block stays in step.
+// States are read out at the step counts read_at[].
 // ---------------------------------------------------------------------------
-template <int KT>
-__global__ __launch_bounds__(256) void k_time_hk(const HkTimeArgs a)
+template <int KT, int RB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB == 2 ? 2 : 1))) void k_time_hk(
+    const HkTimeArgs a)
 {
+    __shared__ f16x8 lds[2 * KT * 4 * 64];
+    __shared__ unsigned long long s_task;
     const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
     for (;;) {
-        unsigned long long tk = 0;
-        if (lane == 0) tk = atomicAdd(a.queue, 1ull);
-        tk = __shfl(tk, 0);
+        if (threadIdx.x == 0) s_task = atomicAdd(a.queue, 1ull);
+        __syncthreads();
+        const unsigned long long tk = s_task;
+        __syncthreads();
         const uint32_t tlo = __builtin_amdgcn_readfirstlane((uint32_t)tk);
         const uint32_t thi = __builtin_amdgcn_readfirstlane((uint32_t)(tk >> 32));
         const int64_t task = (int64_t)(((uint64_t)thi << 32) | tlo);
@@ -324,11 +388,18 @@ __global__ __launch_bounds__(256) void k_time_hk(const HkTimeArgs a)
             np = a.np_arr[b];
             seed = a.seed_arr[b];
         }
+        // a wave serves 16 RB particles: RB = 4 one chunk, RB = 2 half a chunk
+        // (lanes 32..63 then mirror lanes 0..31)
+        constexpr int WPC = 4 / RB;  // waves per chunk
         const int64_t cpo = (np + 63) >> 6;
-        const int64_t ch = task - tb;  // chunk within the set (one per task)
-        const int64_t j = ch / cpo;
-        const int64_t i = (ch - j * cpo) * 64 + lane;
-        const bool act = i < np;
+        const int64_t nch = cpo * a.n_obs;
+        const int64_t ch = (task - tb) * (4 / WPC) + w / WPC;  // this wave's chunk within the set
+        const int part = (w % WPC) * 16 * RB + (lane % (16 * RB));  // particle offset within the chunk
+        const bool wave_on = ch < nch;
+        const bool writer = wave_on && lane < 16 * RB;
+        const int64_t chv = wave_on ? ch : 0;
+        const int64_t j = chv / cpo;
+        const int64_t i = (chv - j * cpo) * 64 + part;
         const uint32_t pi = (uint32_t)i, pj = (uint32_t)j;
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
         const unsigned char *set = a.frag + (int64_t)b * a.set_bytes;
@@ -339,7 +410,7 @@ __global__ __launch_bounds__(256) void k_time_hk(const HkTimeArgs a)
 
         auto step = [&](float z0, float z1) {
             float vx, vy;
-            hk_velocity<KT>(set, a.NT, a.B, x.hi, x.lo, y.hi, y.lo, vx, vy);
+            hk_velocity_block<KT, RB>(set, a.NT, a.B, x.hi, x.lo, y.hi, y.lo, lds, vx, vy);
             x.advance(vx + a.v0x, z0, a.sc);
             y.advance(vy + a.v0y, z1, a.sc);
             x.wrap();
@@ -349,48 +420,51 @@ __global__ __launch_bounds__(256) void k_time_hk(const HkTimeArgs a)
         int64_t next = a.read_at[0];
         auto readout = [&](int64_t done) {
             if (done == next) {
-                double *S = a.states + r * a.read_stride + 2 * ((cb + ch) * 64 + lane);
-                S[0] = x.value();
-                S[1] = y.value();
+                if (writer) {
+                    double *S = a.states + r * a.read_stride + 2 * ((cb + ch) * 64 + part);
+                    S[0] = x.value();
+                    S[1] = y.value();
+                }
                 ++r;
                 next = r < a.n_read ? a.read_at[r] : -1;
             }
         };
-        (void)act;  // lanes past np walk too (finite dummy paths); the payoff masks them
         readout(0);
         int64_t n = 0;
         for (; n + 1 < a.n_steps; n += 2) {
-            const U4 w = philox4x32_10((uint32_t)(n >> 1), pi, pj, 0u, k0, k1);
+            const U4 wd = philox4x32_10((uint32_t)(n >> 1), pi, pj, 0u, k0, k1);
             float z0, z1, z2, z3;
-            box_muller(w.x, w.y, z0, z1);
-            box_muller(w.z, w.w, z2, z3);
+            box_muller(wd.x, wd.y, z0, z1);
+            box_muller(wd.z, wd.w, z2, z3);
             step(z0, z1);
             readout(n + 1);
             step(z2, z3);
             readout(n + 2);
         }
         if (n < a.n_steps) {
-            const U4 w = philox4x32_10((uint32_t)(n >> 1), pi, pj, 0u, k0, k1);
+            const U4 wd = philox4x32_10((uint32_t)(n >> 1), pi, pj, 0u, k0, k1);
             float z0, z1;
-            box_muller(w.x, w.y, z0, z1);
+            box_muller(wd.x, wd.y, z0, z1);
             step(z0, z1);
             readout(n + 1);
         }
     }
 }
 
-// Teacher-forced steps and velocity at given points, through hk_velocity.
-// Each wave takes 64 consecutive entries; lanes past count use the origin.
+// Teacher-forced steps and velocity at given points, through
+// hk_velocity_block.  Each block takes 256 consecutive entries; threads past
+// count use the origin.
 template <int KT>
 __global__ __launch_bounds__(256) void k_step_hk(const HkStepArgs a)
 {
+    __shared__ f16x8 lds[2 * KT * 4 * 64];
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool act = e < a.count;
     Coord<float> x, y;
     x.set(act ? a.X[2 * e] : 0.0);
     y.set(act ? a.X[2 * e + 1] : 0.0);
     float vx, vy;
-    hk_velocity<KT>(a.frag, a.NT, a.B, x.hi, x.lo, y.hi, y.lo, vx, vy);
+    hk_velocity_block<KT, 4>(a.frag, a.NT, a.B, x.hi, x.lo, y.hi, y.lo, lds, vx, vy);
     if (!act) return;
     if (a.V) {
         a.V[2 * e] = (double)(vx + a.v0x);
@@ -422,6 +496,14 @@ int64_t hk_set_bytes(int K)
     return (int64_t)sizeof(HkHeader) + (int64_t)hk_nt(K) * hk_kt(K) * 4 * 64 * 8 * (int64_t)sizeof(_Float16);
 }
 
+// Row blocks (16 particles) per wave in the time kernel: 2 keeps two waves per
+// SIMD resident, so one wave's vector work overlaps the other's matrix work.
+#ifndef HK_RB
+#define HK_RB 2
+#endif
+
+int hk_particles_per_task() { return 4 * 16 * HK_RB; }
+
 hipError_t launch_fold_hk(const HkFoldArgs &a, unsigned char *out, int n_sets, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fold_hk, dim3(n_sets), dim3(256), 0, st, a, out);
@@ -446,14 +528,13 @@ hipError_t launch_time_hk(const HkTimeArgs &a, int n_cu, hipStream_t st)
 {
     return dispatch_kt(a.KT, [&](auto kc) -> hipError_t {
         constexpr int KT = decltype(kc)::value;
-        auto kern = k_time_hk<KT>;
+        auto kern = k_time_hk<KT, HK_RB>;
         int per_cu = 0;
         hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
         if (err != hipSuccess) return err;
         if (per_cu < 1) per_cu = 1;
         int64_t blocks = (int64_t)per_cu * n_cu;
-        const int64_t need = (a.n_tasks + 3) / 4;
-        if (blocks > need) blocks = need;
+        if (blocks > a.n_tasks) blocks = a.n_tasks;  // one task per block
         if (blocks < 1) blocks = 1;
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, st, a);
         return hipGetLastError();

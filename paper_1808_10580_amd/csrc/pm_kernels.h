@@ -131,11 +131,13 @@ int row_stride(int domain, int K);
 // ---------------------------------------------------------------------------
 constexpr int HK_BASIS_SHIFT = 8;  // the basis enters the products scaled by 2^8
 
-struct HkHeader {        // start of each parameter set's coefficient block
-    float inv_scale;     // 2^-(coefficient shift + HK_BASIS_SHIFT)
-    float cmax;          // max |Cx|, |Cy| (FP32)
-    float pad[62];       // tiles start 256 bytes in
+struct HkHeader {              // start of each parameter set's coefficient block
+    float inv_scale;           // 2^-(coefficient shift + HK_BASIS_SHIFT)
+    float cmax;                // max |Cx|, |Cy| (FP32)
+    unsigned char kt_lim[16];  // per nt stage: tiles kt >= kt_lim[nt] are zero in both components
+    float pad[58];             // tiles start 256 bytes in
 };
+static_assert(sizeof(HkHeader) == 256, "tile alignment");
 
 struct HkFoldArgs {
     const int32_t *index;  // device [(2K+1)^2]: mode of (k_x, k_y) at [(k_x+K)(2K+1) + k_y+K], or -1
@@ -157,7 +159,7 @@ struct HkTimeArgs {
     uint64_t seed0;
     const int64_t *np_arr;
     const uint64_t *seed_arr;
-    const int64_t *task_off;   // one task per chunk
+    const int64_t *task_off;   // one task per block: hk_particles_per_task() / 64 chunks of one set
     const int64_t *chunk_off;
     int64_t n_tasks;
     int64_t n_steps;
@@ -187,6 +189,7 @@ struct HkStepArgs {
 
 int hk_kt(int K);
 int hk_nt(int K);
+int hk_particles_per_task();  // particles one block (one task) of the time kernel serves
 int64_t hk_set_bytes(int K);
 hipError_t launch_fold_hk(const HkFoldArgs &a, unsigned char *out, int n_sets, hipStream_t st);
 hipError_t launch_time_hk(const HkTimeArgs &a, int n_cu, hipStream_t st);
