@@ -16,10 +16,13 @@ draws only learns the prior mean of G; the training inputs are pCN moves of
 size 2 beta around the pilot chain's states (where the chains live), their
 outputs the batched particle map at a reduced particle count.
 
-Output: one JSON line with samples/s, particle-map calls, acceptance rates and
-the effective sample size (Geyer) of the misfit trace and of the first 8
-coefficients for both chains, plus the surrogate's training time and held-out
-error.
+Three chains: plain pCN, delayed acceptance with the surrogate misfit at the
+data noise gamma, and delayed acceptance with an approximation-error model
+(stage-1 noise gamma^2 + sigma_j^2, sigma_j the surrogate's held-out error per
+observation).  Output: one JSON line with samples/s, particle-map calls,
+acceptance rates and the effective sample size (Geyer) of the misfit trace and
+of the first 8 coefficients for every chain, plus the surrogate's training
+time and held-out error.
 """
 from __future__ import annotations
 
@@ -32,7 +35,7 @@ import numpy as np
 
 
 def run(n_train=8192, train_particles=10_000, iters=2000, pilot=60, chain_particles=100_000, seed=1808,
-        epochs=200, verbose=True):
+        epochs=200, verbose=True, dump=None, dataset_only=False):
     import torch
 
     import paper_1808_10580_amd as pm
@@ -78,6 +81,13 @@ def run(n_train=8192, train_particles=10_000, iters=2000, pilot=60, chain_partic
     G = particle_dataset(prob, wl, U, train_particles, wl.seed)
     out["dataset_s"] = time.perf_counter() - t0
     out["dataset_particle_steps"] = float(n_train) * wl.n_obs * train_particles * wl.n_steps
+    if dump:
+        np.savez(dump, U=U, G=G, y=y, g_star=g_star, u_star=setup["u_star"], prior_std=prior_std, beta=beta,
+                 pilot=np.array(pc.samples))
+    if dataset_only:
+        prob.close()
+        ctx.close()
+        return out
     sur = Surrogate(ctx, prior_std, wl.n_obs, seed=seed)
     hist = sur.fit(U, G, epochs=epochs, batch=1024, lr=1e-3)
     out["train_s"] = hist["seconds"]
@@ -91,7 +101,7 @@ def run(n_train=8192, train_particles=10_000, iters=2000, pilot=60, chain_partic
 
     coords = list(range(8))
     res = {}
-    for kind in ("plain", "da"):
+    for kind in ("plain", "da", "da_aem"):
         fwd.calls, fwd.seconds = 0, 0.0
         sur_calls = [0]
 
@@ -99,14 +109,15 @@ def run(n_train=8192, train_particles=10_000, iters=2000, pilot=60, chain_partic
             sur_calls[0] += 1
             return sur(u)
 
+        gamma_s = np.sqrt(gamma ** 2 + sur.err_std ** 2) if kind == "da_aem" else None
         c = mcmc.start_chain(setup["u_star"], fwd, y, gamma, seed=seed + 2,
-                             surrogate=surf if kind == "da" else None)
+                             surrogate=surf if kind != "plain" else None, gamma_s=gamma_s)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if kind == "plain":
             mcmc.pcn_steps(c, iters, fwd, prior_std, y, gamma, beta)
         else:
-            mcmc.da_pcn_steps(c, iters, fwd, surf, prior_std, y, gamma, beta)
+            mcmc.da_pcn_steps(c, iters, fwd, surf, prior_std, y, gamma, beta, gamma_s=gamma_s)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         S = np.array(c.samples)
@@ -118,12 +129,13 @@ def run(n_train=8192, train_particles=10_000, iters=2000, pilot=60, chain_partic
                      "surrogate_calls": sur_calls[0]}
         if verbose:
             print(f"[da] {kind}: {res[kind]}", flush=True)
-    out["plain"], out["da"] = res["plain"], res["da"]
-    out["speedup_samples_per_s"] = res["da"]["samples_per_s"] / res["plain"]["samples_per_s"]
-    out["speedup_ess_per_s"] = (res["da"]["ess_per_s"] / res["plain"]["ess_per_s"]
-                                if res["plain"]["ess_per_s"] > 0 else None)
-    out["speedup_ess_phi_per_s"] = (res["da"]["ess_phi_per_s"] / res["plain"]["ess_phi_per_s"]
-                                    if res["plain"]["ess_phi_per_s"] > 0 else None)
+    out.update(res)
+    for kind in ("da", "da_aem"):
+        out[f"{kind}_speedup_samples_per_s"] = res[kind]["samples_per_s"] / res["plain"]["samples_per_s"]
+        out[f"{kind}_speedup_ess_per_s"] = (res[kind]["ess_per_s"] / res["plain"]["ess_per_s"]
+                                            if res["plain"]["ess_per_s"] > 0 else None)
+        out[f"{kind}_speedup_ess_phi_per_s"] = (res[kind]["ess_phi_per_s"] / res["plain"]["ess_phi_per_s"]
+                                                if res["plain"]["ess_phi_per_s"] > 0 else None)
     prob.close()
     ctx.close()
     return out
@@ -135,8 +147,11 @@ def main():
     ap.add_argument("--train-particles", type=int, default=10_000)
     ap.add_argument("--iters", type=int, default=2000)
     ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--dump", default=None, help="save the training set (npz) here")
+    ap.add_argument("--dataset-only", action="store_true", help="stop after the training set")
     a = ap.parse_args()
-    print(json.dumps(run(a.n_train, a.train_particles, a.iters, epochs=a.epochs)))
+    print(json.dumps(run(a.n_train, a.train_particles, a.iters, epochs=a.epochs, dump=a.dump,
+                         dataset_only=a.dataset_only)))
 
 
 if __name__ == "__main__":

@@ -37,10 +37,14 @@ from typing import Callable, Dict, List, Optional
 import numpy as np
 
 
-def misfit(G: np.ndarray, y: np.ndarray, gamma: float) -> float:
-    """Phi = |y - G|^2 / (2 gamma^2) in FP64."""
+def misfit(G: np.ndarray, y: np.ndarray, gamma) -> float:
+    """Phi = |y - G|^2 / (2 gamma^2) in FP64; gamma may be one value or one
+    per observation."""
     r = np.asarray(y, dtype=np.float64) - np.asarray(G, dtype=np.float64)
-    return float(r @ r) / (2.0 * gamma * gamma)
+    if np.ndim(gamma) == 0:
+        return float(r @ r) / (2.0 * gamma * gamma)
+    g = np.asarray(gamma, dtype=np.float64)
+    return float(np.sum(r * r / (2.0 * g * g)))
 
 
 def _gen(seed: int, stream: int) -> np.random.Generator:
@@ -82,11 +86,12 @@ class Chain:
 
 
 def start_chain(u0, forward: Callable, y, gamma: float, seed: int,
-                surrogate: Optional[Callable] = None) -> Chain:
+                surrogate: Optional[Callable] = None, gamma_s=None) -> Chain:
+    """gamma_s: noise level of the stage-1 (surrogate) misfit, default gamma."""
     u0 = np.array(u0, dtype=np.float64)
     c = Chain(u=u0, phi=misfit(forward(u0), y, gamma))
     if surrogate is not None:
-        c.phi_s = misfit(surrogate(u0), y, gamma)
+        c.phi_s = misfit(surrogate(u0), y, gamma if gamma_s is None else gamma_s)
     c.rng_prop, c.rng_s1, c.rng_s2 = _gen(seed, 0), _gen(seed, 1), _gen(seed, 2)
     return c
 
@@ -117,13 +122,18 @@ def pcn_steps(c: Chain, n: int, forward: Callable, prior_std, y, gamma: float, b
 
 
 def da_pcn_steps(c: Chain, n: int, forward: Callable, surrogate: Callable, prior_std, y,
-                 gamma: float, beta: float, keep_every: int = 1) -> Chain:
+                 gamma: float, beta: float, keep_every: int = 1, gamma_s=None) -> Chain:
     """n delayed-acceptance pCN iterations: the surrogate screens, the particle
-    map decides."""
+    map decides.  gamma_s (scalar or per observation; default gamma) is the
+    noise level of the stage-1 misfit: widening it by the surrogate's own
+    error, gamma_s^2 = gamma^2 + sigma_j^2 (an approximation-error model),
+    makes stage 1 reject fewer proposals the particle map would accept.  Any
+    gamma_s leaves the chain exact: stage 2 divides the stage-1 ratio out."""
     prior_std = np.asarray(prior_std, dtype=np.float64)
+    gs = gamma if gamma_s is None else gamma_s
     for _ in range(n):
         v = _propose(c, prior_std, beta)
-        phis_v = misfit(surrogate(v), y, gamma)
+        phis_v = misfit(surrogate(v), y, gs)
         log_a1 = c.phi_s - phis_v
         passed = log_a1 >= 0.0 or math.log(c.rng_s1.random()) < log_a1
         if passed:

@@ -70,6 +70,11 @@ class Surrogate:
         torch.cuda.synchronize()
         hist["seconds"] = time.perf_counter() - t0
         hist["val_idx"] = val
+        # held-out error per observation (physical units): the approximation
+        # error a delayed-acceptance stage 1 can add to the data noise
+        pv = self.predict(U[val])
+        self.err_std = np.sqrt(np.mean((pv - G[val]) ** 2, axis=0))
+        hist["err_std"] = self.err_std
         return hist
 
     def predict(self, U: np.ndarray) -> np.ndarray:

@@ -3,7 +3,8 @@
   - Phi = 0: every proposal is accepted and the chain samples the prior;
   - linear-Gaussian problem G(u) = A u: the posterior is Gaussian with
     covariance (A^T A / gamma^2 + C^-1)^-1 and mean Sigma A^T y / gamma^2;
-    plain and delayed-acceptance chains both recover it;
+    plain and delayed-acceptance chains both recover it, also with a widened
+    (approximation-error) stage-1 noise level;
   - delayed acceptance with Phi~ = 0 reproduces plain pCN bit for bit;
   - checkpoint + resume reproduces an uninterrupted chain bit for bit;
   - the ESS estimator recovers n (1 - rho) / (1 + rho) for an AR(1) chain.
@@ -42,20 +43,22 @@ def test_zero_misfit_samples_the_prior():
     assert np.all(np.abs(S.std(0) / std - 1) < 6 / math.sqrt(e))
 
 
-@pytest.mark.parametrize("kind", ["plain", "da"])
+@pytest.mark.parametrize("kind", ["plain", "da", "da_aem"])
 def test_linear_gaussian_posterior(kind):
     A, std, y, gamma, mu, Sigma = _lin_problem()
     fwd = lambda u: A @ u
     # a deliberately imperfect surrogate (perturbed operator) for delayed acceptance
     A2 = A * 1.05 + 0.02
     sur = lambda u: A2 @ u
+    # a widened stage-1 noise level (per observation) must not change the target
+    gamma_s = gamma * np.linspace(1.0, 2.0, A.shape[0]) if kind == "da_aem" else None
     c = mcmc.start_chain(np.zeros(A.shape[1]), fwd, y, gamma, seed=11,
-                         surrogate=sur if kind == "da" else None)
+                         surrogate=sur if kind != "plain" else None, gamma_s=gamma_s)
     n = 60000
     if kind == "plain":
         mcmc.pcn_steps(c, n, fwd, std, y, gamma, beta=0.3)
     else:
-        mcmc.da_pcn_steps(c, n, fwd, sur, std, y, gamma, beta=0.3)
+        mcmc.da_pcn_steps(c, n, fwd, sur, std, y, gamma, beta=0.3, gamma_s=gamma_s)
         assert c.n_forward < n  # stage 1 screened some proposals
     S = np.array(c.samples)[5000:]
     sd = np.sqrt(np.diag(Sigma))
