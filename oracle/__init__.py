@@ -267,6 +267,24 @@ def observe_time_multi(modes, u, theta0, obs, kappa, read_steps, dt, n_particles
     return np.array(ms), np.array(vs)
 
 
+def jacobian_time(modes, u, theta0, obs, kappa, T, dt, n_particles, seed, h, v0=(0.0, 0.0)):
+    """Central finite differences of Algorithm 1's G with common random
+    numbers (the same seed for every evaluation):
+        J[j][k] = (G_j(u + h e_k) - G_j(u - h e_k)) / ((u_k + h) - (u_k - h)).
+    Returns J [n_obs, 2M]."""
+    u = np.asarray(u, dtype=np.float64)
+    n = u.size
+    cols = []
+    for k in range(n):
+        up, um = u.copy(), u.copy()
+        up[k] = u[k] + h
+        um[k] = u[k] - h
+        gp, _ = observe_time(modes, up, theta0, obs, kappa, T, dt, n_particles, seed, v0)
+        gm, _ = observe_time(modes, um, theta0, obs, kappa, T, dt, n_particles, seed, v0)
+        cols.append((gp - gm) / (up[k] - um[k]))
+    return np.stack(cols, axis=1)
+
+
 def observe_dirichlet_paths(modes, u, f, g, obs, kappa, dt, n_particles, seed, max_steps,
                             v0=(0.0, 0.0)):
     """Algorithm 2 on the unit disk: per-particle payoffs, exit steps, capped flags
