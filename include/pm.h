@@ -186,6 +186,21 @@ int pm_observe_time_batch(pm_ctx *ctx, const pm_problem *p, int n_u, const doubl
                           const double *obs_pts, int n_obs, double kappa, double T, double dt,
                           double *mean, double *var);
 
+/* Finite-difference Jacobian of the time-problem map G (Algorithm 1):
+ *   J[j][k] = (G_j(u + h e_k) - G_j(u - h e_k)) / ((u_k + h) - (u_k - h)),
+ * the derivative of G with respect to each of the 2M coefficients, for
+ * gradient-based optimisation or samplers (the paper's methods need it from
+ * repeated forward maps, its G having no adjoint).  All 4M perturbed maps run
+ * in one batched launch with common random numbers (one seed and particle
+ * count for every set), so G is a smooth function of u and the differences
+ * carry no independent Monte Carlo noise.
+ *   u device [2M] FP64, obs_pts device [n_obs][2], h > 0 (coefficient units)
+ *   J device [n_obs][2M] FP64
+ * Other arguments as for pm_observe_time.  Workspace: 4M x 2M doubles for the
+ * perturbed sets plus the batch's own. */
+int pm_jacobian_time(pm_ctx *ctx, const pm_problem *p, const double *u, const double *obs_pts, int n_obs,
+                     double kappa, double T, double dt, int64_t n_particles, uint64_t seed, double h, double *J);
+
 /* One Euler-Maruyama step per entry (eq. euler), for replaying or checking
  * paths: Y[e] = step n[e] of particle (i[e], j[e]) applied to X[e], in the
  * problem's precision (X is rounded to it first).  Device arrays:

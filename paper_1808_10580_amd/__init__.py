@@ -80,6 +80,7 @@ def _declare(L):
     L.pm_observe_time.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _d, _i64, _u64, _vp, _vp, _vp]
     L.pm_observe_time_multi.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp, C.c_int, _d, _d, _i64, _u64,
                                         _vp, _vp]
+    L.pm_jacobian_time.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _d, _i64, _u64, _d, _vp]
     L.pm_observe_time_batch.argtypes = [_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.c_int, _d, _d, _d,
                                         _vp, _vp]
     L.pm_observe_dirichlet.argtypes = [_vp, _vp, _vp, C.POINTER(_Field), C.POINTER(_Field), _vp,
@@ -296,6 +297,18 @@ class Problem:
                                           _ptr(mean), _ptr(var))
         _check(st, "pm_observe_time_multi")
         return mean, var
+
+    def jacobian_time(self, u, obs, kappa, T, dt, n_particles, seed, h):
+        """Central-difference Jacobian dG/du [n_obs, 2M] with common random numbers (one batched launch)."""
+        torch = _torch()
+        self.ctx.bind_stream()
+        ut = self._u(u)
+        ob = _dev(obs, torch.float64, self.ctx.device).reshape(-1, 2)
+        J = torch.empty((ob.shape[0], 2 * self.n_modes), dtype=torch.float64, device=self.ctx.device)
+        st = _lib().pm_jacobian_time(self.ctx.h, self.h, _ptr(ut), _ptr(ob), ob.shape[0], float(kappa), float(T),
+                                     float(dt), int(n_particles), int(seed), float(h), _ptr(J))
+        _check(st, "pm_jacobian_time")
+        return J
 
     def observe_time_batch(self, U, n_particles: Sequence[int], seeds: Sequence[int], obs, kappa, T, dt):
         torch = _torch()

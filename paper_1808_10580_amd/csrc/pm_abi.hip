@@ -43,6 +43,10 @@ struct pm_ctx {
     size_t nsteps_cap = 0;
     void *order = nullptr;
     size_t order_cap = 0;
+    void *fd_u = nullptr;  // finite differences: perturbed sets, their means and variances
+    size_t fd_u_cap = 0;
+    void *fd_m = nullptr;
+    size_t fd_m_cap = 0;
     void *meta = nullptr;
     size_t meta_cap = 0;
     int64_t *h_meta = nullptr;  // pinned staging for batch metadata
@@ -675,7 +679,7 @@ void pm_destroy(pm_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     void *bufs[] = {c->d_flags, c->d_queue, c->coef, c->part, c->part2, c->pay, c->tau, c->capped,
-                    c->meta, c->states, c->exitp, c->integ, c->nsteps, c->order};
+                    c->meta, c->states, c->exitp, c->integ, c->nsteps, c->order, c->fd_u, c->fd_m};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->h_meta) (void)hipHostFree(c->h_meta);
@@ -847,6 +851,35 @@ int pm_observe_time_multi(pm_ctx *c, const pm_problem *p, const double *u, const
                                          nullptr);
     return observe_time_core<float>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, dt, reads, n_read, mean, var,
                                     nullptr);
+}
+
+int pm_jacobian_time(pm_ctx *c, const pm_problem *p, const double *u, const double *obs, int n_obs,
+                     double kappa, double T, double dt, int64_t np, uint64_t seed, double h, double *J)
+{
+    if (!ctx_ok(c, p)) return PM_EINVAL;
+    if (p->domain != PM_TORUS || !p->has_theta0) return PM_EINVAL;
+    if (p->n_modes < 1 || bad_ptr(u) || bad_ptr(obs) || bad_ptr(J) || n_obs < 1) return PM_EINVAL;
+    if (np < 1 || np > ((int64_t)1 << 32)) return PM_EINVAL;
+    if (!finite_pos(h)) return PM_EINVAL;
+    if (check_time_args(kappa, T, dt)) return PM_EINVAL;
+    const int n_coef = 2 * p->n_modes;
+    const int n_u = 2 * n_coef;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    int st = ensure(c, &c->fd_u, &c->fd_u_cap, (size_t)n_u * n_coef * sizeof(double));
+    if (st) return st;
+    if ((st = ensure(c, &c->fd_m, &c->fd_m_cap, 2 * (size_t)n_u * n_obs * sizeof(double)))) return st;
+    double *U = (double *)c->fd_u, *M = (double *)c->fd_m;
+    if (launch_fd_sets(u, n_coef, h, U, c->stream) != hipSuccess) return PM_EDEVICE;
+    // common random numbers: every set has the same particle count and seed
+    std::vector<int64_t> nps(n_u, np);
+    std::vector<uint64_t> seeds(n_u, seed);
+    st = p->prec == PM_FP64
+             ? observe_time_impl<double>(c, p, n_u, U, nps.data(), seeds.data(), obs, n_obs, kappa, T, dt, M,
+                                         M + (size_t)n_u * n_obs, nullptr)
+             : observe_time_impl<float>(c, p, n_u, U, nps.data(), seeds.data(), obs, n_obs, kappa, T, dt, M,
+                                        M + (size_t)n_u * n_obs, nullptr);
+    if (st) return st;
+    return launch_fd_diff(U, M, n_obs, n_coef, J, c->stream) == hipSuccess ? PM_OK : PM_EDEVICE;
 }
 
 int pm_observe_time_batch(pm_ctx *c, const pm_problem *p, int n_u, const double *u,

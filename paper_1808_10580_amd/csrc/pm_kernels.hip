@@ -613,6 +613,50 @@ __global__ void k_zero_u64(unsigned long long *p, int n)
 }
 
 // ---------------------------------------------------------------------------
+// Finite differences: set 2k is u + h e_k, set 2k+1 is u - h e_k; the
+// Jacobian divides the difference of their means by the difference of the
+// coefficients actually evaluated (u_k + h) - (u_k - h).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fd_sets(const double *__restrict__ u, int n_coef, double h,
+                                                 double *__restrict__ U)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = 2 * (int64_t)n_coef * n_coef;
+    if (e >= total) return;
+    const int64_t set = e / n_coef;
+    const int c = (int)(e - set * n_coef);
+    const int k = (int)(set >> 1);
+    double v = u[c];
+    if (c == k) v = (set & 1) ? v - h : v + h;
+    U[e] = v;
+}
+
+__global__ __launch_bounds__(256) void k_fd_diff(const double *__restrict__ U, const double *__restrict__ mean,
+                                                 int n_obs, int n_coef, double *__restrict__ J)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n_obs * n_coef) return;
+    const int j = (int)(e / n_coef), k = (int)(e - (int64_t)j * n_coef);
+    const double dk = U[(int64_t)(2 * k) * n_coef + k] - U[(int64_t)(2 * k + 1) * n_coef + k];
+    J[e] = (mean[(int64_t)(2 * k) * n_obs + j] - mean[(int64_t)(2 * k + 1) * n_obs + j]) / dk;
+}
+
+hipError_t launch_fd_sets(const double *u, int n_coef, double h, double *U, hipStream_t st)
+{
+    const int64_t total = 2 * (int64_t)n_coef * n_coef;
+    hipLaunchKernelGGL(k_fd_sets, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, u, n_coef, h, U);
+    return hipGetLastError();
+}
+
+hipError_t launch_fd_diff(const double *U, const double *mean, int n_obs, int n_coef, double *J, hipStream_t st)
+{
+    const int64_t total = (int64_t)n_obs * n_coef;
+    hipLaunchKernelGGL(k_fd_diff, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, U, mean, n_obs, n_coef,
+                       J);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Replay / inspection hooks (same device functions as the main kernels).
 // ---------------------------------------------------------------------------
 template <typename T, int K>
