@@ -23,8 +23,8 @@ _SRC = os.path.join(_HERE, "pm_oracle.c")
 _LIB = os.path.join(_HERE, "_build", "liboracle.so")
 
 FIELD_CODES = {"zero": 0, "const": 1, "sinsin": 2, "fourier": 3, "gauss_periodic": 4,
-               "cos_m_theta": 5, "exp_linear": 6, "linear": 7}
-DOMAIN_CODES = {"torus": 0, "disk": 1}
+               "cos_m_theta": 5, "exp_linear": 6, "linear": 7, "gauss": 8, "cos_axes": 9}
+DOMAIN_CODES = {"torus": 0, "disk": 1, "square": 2}
 
 
 def build(force: bool = True) -> str:
@@ -286,9 +286,10 @@ def jacobian_time(modes, u, theta0, obs, kappa, T, dt, n_particles, seed, h, v0=
 
 
 def observe_dirichlet_paths(modes, u, f, g, obs, kappa, dt, n_particles, seed, max_steps,
-                            v0=(0.0, 0.0)):
-    """Algorithm 2 on the unit disk: per-particle payoffs, exit steps, capped flags
-    and exit points, each [n_obs, Np] (exit points [n_obs, Np, 2])."""
+                            v0=(0.0, 0.0), domain="disk"):
+    """Algorithm 2 on the unit disk or the unit square: per-particle payoffs,
+    exit steps, capped flags and exit points, each [n_obs, Np] (exit points
+    [n_obs, Np, 2])."""
     keep = _Keep()
     obs = keep.arr(np.asarray(obs, dtype=np.float64).reshape(-1, 2), np.float64)
     n_obs = obs.shape[0]
@@ -297,7 +298,7 @@ def observe_dirichlet_paths(modes, u, f, g, obs, kappa, dt, n_particles, seed, m
     tau = np.zeros((n_obs, Np), dtype=np.int64)
     cap = np.zeros((n_obs, Np), dtype=np.uint8)
     ex = np.zeros((n_obs, Np, 2))
-    fl = _flow(keep, "disk", modes, u, v0)
+    fl = _flow(keep, domain, modes, u, v0)
     ff = _field(keep, f)
     gg = _field(keep, g)
     lib().orc_observe_dirichlet(C.byref(fl), C.byref(ff), C.byref(gg), _ptr(obs, C.c_double),
@@ -324,13 +325,31 @@ def observe_time(modes, u, theta0, obs, kappa, T, dt, n_particles, seed, v0=(0.0
 
 
 def observe_dirichlet(modes, u, f, g, obs, kappa, dt, n_particles, seed, max_steps,
-                      v0=(0.0, 0.0)):
+                      v0=(0.0, 0.0), domain="disk"):
     """G_j(u) of Algorithm 2: mean/var of the payoff and of the exit time."""
-    r = observe_dirichlet_paths(modes, u, f, g, obs, kappa, dt, n_particles, seed, max_steps, v0)
+    r = observe_dirichlet_paths(modes, u, f, g, obs, kappa, dt, n_particles, seed, max_steps, v0, domain)
     m, v = mean_var(r["payoff"])
     tm, tv = mean_var(r["tau_steps"].astype(np.float64) * dt)
     return {"mean": m, "var": v, "tau_mean": tm, "tau_var": tv,
             "n_capped": r["capped"].sum(axis=1)}
+
+
+def observe_dirichlet_sources(modes, u, g, obs, kappa, dt, n_particles, seed, max_steps, sources,
+                              v0=(0.0, 0.0), domain="square"):
+    """Theorem 3.2 with a source f = sum_j f_j phi_j, phi_j(x) = exp(-w_j |x - c_j|^2):
+    theta(x_i) = E[theta_dD(X_tau)] - sum_j f_j E[int_0^tau phi_j(X_t) dt], so on common
+    random numbers G(F) = a - B F exactly.  a (with its variance) comes from a run with
+    f = 0, column j of B from a run with g = 0 and f = phi_j (payoff -int phi_j).
+    sources: [(cx, cy, w), ...].  Returns (a_mean, a_var, B [n_obs, n_src], tau_mean)."""
+    r0 = observe_dirichlet(modes, u, {"kind": "zero", "params": []}, g, obs, kappa, dt, n_particles, seed,
+                           max_steps, v0, domain)
+    cols = []
+    for cx, cy, w in sources:
+        rj = observe_dirichlet(modes, u, {"kind": "gauss", "params": [cx, cy, w, 1.0]},
+                               {"kind": "zero", "params": []}, obs, kappa, dt, n_particles, seed, max_steps,
+                               v0, domain)
+        cols.append(-rj["mean"])
+    return r0["mean"], r0["var"], np.stack(cols, axis=1), r0["tau_mean"]
 
 
 def num_threads() -> int:

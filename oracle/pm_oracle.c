@@ -102,7 +102,9 @@ enum {
     ORC_F_GAUSS_PERIODIC = 4,
     ORC_F_COS_M_THETA = 5,
     ORC_F_EXP_LINEAR = 6,
-    ORC_F_LINEAR = 7
+    ORC_F_LINEAR = 7,
+    ORC_F_GAUSS = 8,
+    ORC_F_COS_AXES = 9
 };
 
 typedef struct {
@@ -144,6 +146,14 @@ double orc_field_eval(const orc_field *f, double x, double y)
         return exp(p[0] * x + p[1] * y);
     case ORC_F_LINEAR:
         return p[0] * x + p[1] * y + p[2];
+    case ORC_F_GAUSS: /* sum_m A_m exp(-w_m |x - c_m|^2), not periodised */
+        for (int m = 0; m + 3 < f->n_params; m += 4) {
+            double dx = x - p[m], dy = y - p[m + 1];
+            s += p[m + 3] * exp(-p[m + 2] * (dx * dx + dy * dy));
+        }
+        return s;
+    case ORC_F_COS_AXES: /* A (cos(w x) + cos(w y)) */
+        return p[0] * (cos(p[1] * x) + cos(p[1] * y));
     default:
         return NAN;
     }
@@ -154,7 +164,8 @@ double orc_field_eval(const orc_field *f, double x, double y)
 /* u = [a_0..a_{M-1}, b_0..b_{M-1}], mode m has wavevector k[2m], k[2m+1].  */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    int domain;            /* 0 torus [0,1)^2, 1 unit disk */
+    int domain;            /* 0 torus [0,1)^2, 1 unit disk, 2 unit square [0,1]^2 (the
+                              periodic Fourier field evaluated on it, no cutoff) */
     int n_modes;
     const int32_t *k;      /* [n_modes][2] */
     const double *u;       /* [2 n_modes] */
@@ -303,12 +314,31 @@ void orc_observe_time_steps(const orc_flow *fl, const orc_field *theta0, const d
     }
 }
 
+/* Has the step left the domain?  If so, the exit point: the nearest point of
+   the boundary (disk: radial projection Y/|Y|; square: Y clamped to
+   [0,1]^2, coordinate by coordinate). */
+static int left_domain(int domain, const double Y[2], double E[2])
+{
+    if (domain == 2) {
+        if (Y[0] > 0.0 && Y[0] < 1.0 && Y[1] > 0.0 && Y[1] < 1.0) return 0;
+        E[0] = Y[0] < 0.0 ? 0.0 : (Y[0] > 1.0 ? 1.0 : Y[0]);
+        E[1] = Y[1] < 0.0 ? 0.0 : (Y[1] > 1.0 ? 1.0 : Y[1]);
+        return 1;
+    }
+    double r2 = Y[0] * Y[0] + Y[1] * Y[1];
+    if (r2 < 1.0) return 0;
+    double r = sqrt(r2);
+    E[0] = Y[0] / r;
+    E[1] = Y[1] / r;
+    return 1;
+}
+
 /*
- * Algorithm 2 on the unit disk D = {|x| < 1}.
+ * Algorithm 2 on the unit disk D = {|x| < 1} or the unit square (0,1)^2.
  *   X = x_j, I = 0, n = 0
  *   repeat:  Y = EM step of X (step index n); I += f(X) dt; n += 1
- *            if |Y|^2 >= 1: exit point X_tau = Y/|Y| (radial projection onto
- *                           the boundary), tau = n dt, stop
+ *            if Y is not in D: exit point X_tau = the nearest boundary point
+ *                              to Y (left_domain), tau = n dt, stop
  *            X = Y; if n == max_steps: the path is capped, stop
  *   payoff = theta_dD(X_tau) - I     (Theorem 3.2)
  * A capped path never reached the boundary (chi_{tau<inf} = 0 in Theorem 3.2
@@ -335,11 +365,7 @@ void orc_observe_dirichlet(const orc_flow *fl, const orc_field *f, const orc_fie
             em_step(fl, kappa, dt, seed, (uint64_t)n, (uint32_t)i, (uint32_t)j, X, Y);
             I += orc_field_eval(f, X[0], X[1]) * dt;
             n += 1;
-            double r2 = Y[0] * Y[0] + Y[1] * Y[1];
-            if (r2 >= 1.0) {
-                double r = sqrt(r2);
-                E[0] = Y[0] / r;
-                E[1] = Y[1] / r;
+            if (left_domain(fl->domain, Y, E)) {
                 exited = 1;
                 break;
             }

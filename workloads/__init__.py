@@ -36,6 +36,8 @@ FIELD_KINDS = {
     "cos_m_theta": "f(x) = cos(m * atan2(y, x))                params [m]",
     "exp_linear": "f(x) = exp(c0 x + c1 y)                    params [c0,c1]",
     "linear": "f(x) = c0 x + c1 y + c2                    params [c0,c1,c2]",
+    "gauss": "f(x) = sum_m A_m exp(-w_m |x - c_m|^2)      params [cx,cy,w,A]*n",
+    "cos_axes": "f(x) = A (cos(w x) + cos(w y))             params [A, w]",
 }
 
 
@@ -249,6 +251,22 @@ def turbulent_k80(seed: int = WORKLOAD_SEED, n_particles: int = 100_000) -> Work
                     extra={"read_steps": reads})
 
 
+def bvp_square(seed: int = WORKLOAD_SEED, n_particles: int = 100_000) -> Workload:
+    """The paper's optimal-forcing example (Problem 2.2 on the unit square):
+    -(1,1).grad theta + kappa Lap theta = sum_j f_j exp(-4 |x - x_f^(j)|^2),
+    theta = (cos(pi x / 2) + cos(pi y / 2)) / 2 on the boundary, kappa = 0.282,
+    three observation points, data y = [0, 0, 0].  The forcing and observation
+    locations appear only in a figure of the paper: here they are seeded
+    uniform draws in [0.15, 0.85]^2.  dt = 1e-4, 1e5 particles per point."""
+    rng = np.random.default_rng([seed, 8])
+    sources = [(float(cx), float(cy), 4.0) for cx, cy in 0.15 + 0.7 * rng.random((3, 2))]
+    obs = 0.15 + 0.7 * rng.random((3, 2))
+    return Workload("square-bvp", "square", np.zeros((0, 2), dtype=np.int32), np.zeros(0), obs, kappa=0.282,
+                    dt=1e-4, n_particles=n_particles, seed=8, prec="fp64", v0=(1.0, 1.0),
+                    g=fld("cos_axes", [0.5, math.pi / 2]), max_steps=10_000_000,
+                    extra={"sources": sources, "data": np.zeros(3)})
+
+
 def surrogate_setup(seed: int = WORKLOAD_SEED) -> dict:
     """Inputs of the delayed-acceptance study: the true parameter u*, the noise level
     and the standard-normal draws that make the synthetic data y = G(u*) + gamma*eta."""
@@ -265,4 +283,5 @@ WORKLOADS = {
     "disk-dirichlet": dirichlet_main,
     "torus-k6-batch": batch_main,
     "torus-k80-turbulent": turbulent_k80,
+    "square-bvp": bvp_square,
 }
