@@ -63,7 +63,7 @@ enum pm_status {
     PM_EUNSUPPORTED = -6  /* valid request outside the compiled kernel set */
 };
 
-enum pm_domain { PM_TORUS = 0, PM_DISK = 1 };
+enum pm_domain { PM_TORUS = 0, PM_DISK = 1, PM_SQUARE = 2 };
 enum pm_prec { PM_FP32 = 0, PM_FP64 = 1 };
 
 /* Scalar fields theta0 (initial condition), theta_dD (boundary data) and
@@ -76,10 +76,13 @@ enum pm_prec { PM_FP32 = 0, PM_FP64 = 1 };
  *   PM_F_COS_M_THETA     cos(m atan2(y,x))                       [m]
  *   PM_F_EXP_LINEAR      exp(c0 x + c1 y)                        [c0,c1]
  *   PM_F_LINEAR          c0 x + c1 y + c2                        [c0,c1,c2]
+ *   PM_F_GAUSS           sum_m A_m exp(-w_m |x - c_m|^2)         [cx,cy,w,A] per term
+ *   PM_F_COS_AXES        A (cos(w x) + cos(w y))                 [A, w]
  */
 enum pm_field_kind {
     PM_F_ZERO = 0, PM_F_CONST = 1, PM_F_SINSIN = 2, PM_F_FOURIER = 3,
-    PM_F_GAUSS_PERIODIC = 4, PM_F_COS_M_THETA = 5, PM_F_EXP_LINEAR = 6, PM_F_LINEAR = 7
+    PM_F_GAUSS_PERIODIC = 4, PM_F_COS_M_THETA = 5, PM_F_EXP_LINEAR = 6, PM_F_LINEAR = 7,
+    PM_F_GAUSS = 8, PM_F_COS_AXES = 9
 };
 #define PM_FIELD_MAX_PARAMS 32
 
@@ -108,7 +111,9 @@ void pm_destroy(pm_ctx *ctx);
 int pm_set_stream(pm_ctx *ctx, void *stream);
 
 /* Problem handle: what a chain or an optimiser does not vary.
- *   domain   PM_TORUS (Problem 2.1 on [0,1)^2) or PM_DISK (Problem 2.2 on
+ *   domain   PM_TORUS (Problem 2.1 on [0,1)^2), PM_SQUARE (Problem 2.2 on
+ *            the unit square (0,1)^2, velocity = the periodic Fourier field
+ *            of eq. v_expand evaluated on it, plus v0) or PM_DISK (Problem 2.2 on
  *            the unit disk)
  *   n_modes  M >= 0, k: host [M][2] int32 wavevectors, |k_x|,|k_y| <= PM_MAX_K
  *            (<= PM_MAX_K_MFMA for PM_TORUS with PM_FP32; then no wavevector
@@ -134,6 +139,26 @@ int pm_observe_time(pm_ctx *ctx, const pm_problem *p, const double *u, const dou
                     int n_obs, double kappa, double T, double dt, int64_t n_particles,
                     uint64_t seed, double *mean, double *var, double *endpoints);
 
+/* Gaussian sources with unknown weights (the optimal-forcing example of
+ * Section 4): for f = sum_q f_q phi_q, phi_q(x) = exp(-w_q |x - c_q|^2),
+ * Theorem 3.2 gives theta(x_i) = a_i - sum_q B_qi f_q with
+ *   a_i  = E[theta_dD(X_tau)]            (0 for a capped path)
+ *   B_qi = E[int_0^tau phi_q(X_t) dt]   (left-point rule),
+ * so one particle run, recording one integral per source along each path,
+ * gives G(F) = a - B^T F for every F (common random numbers make it exact).
+ *   PM_SQUARE problems only (else PM_EUNSUPPORTED); 1 <= n_src <= PM_MAX_SOURCES
+ *   sources   host [n_src][3] = (cx, cy, w)
+ *   bnd_mean, bnd_var  device [n_obs]: mean and variance of theta_dD(X_tau)
+ *   src_mean  device [n_src][n_obs]: B
+ *   tau_mean, tau_var, n_capped as for pm_observe_dirichlet
+ * The exit rule is that of pm_observe_dirichlet on the square. */
+#define PM_MAX_SOURCES 4
+int pm_observe_dirichlet_sources(pm_ctx *ctx, const pm_problem *p, const double *u, const pm_field *g,
+                                 const double *obs_pts, int n_obs, double kappa, double dt, int64_t n_particles,
+                                 uint64_t seed, int64_t max_steps, int n_src, const double *sources,
+                                 double *bnd_mean, double *bnd_var, double *src_mean, double *tau_mean,
+                                 double *tau_var, int64_t *n_capped);
+
 /* Observations at several times along the same paths.  The data of an
  * inverse problem may observe theta at times t_1 < ... < t_R at each point
  * (Section 2: observations are pairs (t_j, x_j); Example 3 of Section 4 reads
@@ -155,12 +180,13 @@ int pm_observe_time_multi(pm_ctx *ctx, const pm_problem *p, const double *u, con
                           int n_obs, const int64_t *read_steps, int n_read, double kappa, double dt,
                           int64_t n_particles, uint64_t seed, double *mean, double *var);
 
-/* Algorithm 2 (Section 3.2, Theorem 3.2) on the unit disk:
+/* Algorithm 2 (Section 3.2, Theorem 3.2) on the unit disk or the unit square:
  *   payoff_i = theta_dD(X_tau) - int_0^tau f(X_t) dt
- * with the exit detected when |Y|^2 >= 1 after a step (tested in FP64), the
- * exit point projected radially onto the circle (FP64), tau = n dt for the
- * first outside step n and the source integrated by the left-point rule in
- * FP64.  A path still inside after max_steps steps is capped: its payoff is
+ * with the exit detected after a step when Y is no longer inside (disk:
+ * |Y|^2 >= 1; square: a coordinate <= 0 or >= 1; tested in FP64), the exit
+ * point the nearest boundary point (disk: radial projection; square: Y
+ * clamped to [0,1]^2; FP64), tau = n dt for the first outside step n and the
+ * source integrated by the left-point rule in FP64.  A path still inside after max_steps steps is capped: its payoff is
  * -int f (no boundary term), it is counted in n_capped and pm_sync() returns
  * PM_ECAPPED.
  *   f, g      host field descriptors (source and boundary data)

@@ -22,10 +22,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpm.so")
 
 PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_ENONFINITE, PM_ECAPPED, PM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-TORUS, DISK = 0, 1
+TORUS, DISK, SQUARE = 0, 1, 2
 FP32, FP64 = 0, 1
 FIELD_KINDS = {"zero": 0, "const": 1, "sinsin": 2, "fourier": 3, "gauss_periodic": 4,
-               "cos_m_theta": 5, "exp_linear": 6, "linear": 7}
+               "cos_m_theta": 5, "exp_linear": 6, "linear": 7, "gauss": 8, "cos_axes": 9}
+MAX_SOURCES = 4
 MAX_K = 8
 
 
@@ -81,6 +82,8 @@ def _declare(L):
     L.pm_observe_time_multi.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp, C.c_int, _d, _d, _i64, _u64,
                                         _vp, _vp]
     L.pm_jacobian_time.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _d, _i64, _u64, _d, _vp]
+    L.pm_observe_dirichlet_sources.argtypes = [_vp, _vp, _vp, C.POINTER(_Field), _vp, C.c_int, _d, _d, _i64,
+                                               _u64, _i64, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.pm_observe_time_batch.argtypes = [_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.c_int, _d, _d, _d,
                                         _vp, _vp]
     L.pm_observe_dirichlet.argtypes = [_vp, _vp, _vp, C.POINTER(_Field), C.POINTER(_Field), _vp,
@@ -237,7 +240,7 @@ class Problem:
         th = _FieldHolder(theta0) if theta0 is not None else None
         h = C.c_void_p()
         st = _lib().pm_problem_create(
-            ctx.h, C.byref(h), {"torus": TORUS, "disk": DISK}[domain], self.n_modes,
+            ctx.h, C.byref(h), {"torus": TORUS, "disk": DISK, "square": SQUARE}[domain], self.n_modes,
             C.c_void_p(self.modes.ctypes.data) if self.n_modes else None, C.c_void_p(v0a.ctypes.data),
             C.byref(th.s) if th is not None else None, {"fp32": FP32, "fp64": FP64}[prec])
         _check(st, "pm_problem_create")
@@ -368,6 +371,29 @@ class Problem:
         _check(st, "pm_observe_dirichlet")
         if paths:
             out["paths"] = pt
+        return out
+
+    def observe_dirichlet_sources(self, u, g: dict, obs, kappa, dt, n_particles, seed, max_steps, sources):
+        """Theorem 3.2 split by Gaussian sources (PM_SQUARE): a = E[theta_dD(X_tau)] and
+        B[q, i] = E[int phi_q(X_t) dt], so G(F) = a - B^T F.  sources: [(cx, cy, w), ...]."""
+        torch = _torch()
+        self.ctx.bind_stream()
+        ut = self._u(u)
+        ob = _dev(obs, torch.float64, self.ctx.device).reshape(-1, 2)
+        n_obs = ob.shape[0]
+        src = np.ascontiguousarray(np.asarray(sources, dtype=np.float64).reshape(-1, 3))
+        dev = self.ctx.device
+        out = {k: torch.empty(n_obs, dtype=torch.float64, device=dev)
+               for k in ("bnd_mean", "bnd_var", "tau_mean", "tau_var")}
+        out["B"] = torch.empty((src.shape[0], n_obs), dtype=torch.float64, device=dev)
+        out["n_capped"] = torch.empty(n_obs, dtype=torch.int64, device=dev)
+        gg = _FieldHolder(g)
+        st = _lib().pm_observe_dirichlet_sources(
+            self.ctx.h, self.h, _ptr(ut), C.byref(gg.s), _ptr(ob), n_obs, float(kappa), float(dt),
+            int(n_particles), int(seed), int(max_steps), int(src.shape[0]), C.c_void_p(src.ctypes.data),
+            _ptr(out["bnd_mean"]), _ptr(out["bnd_var"]), _ptr(out["B"]), _ptr(out["tau_mean"]),
+            _ptr(out["tau_var"]), _ptr(out["n_capped"]))
+        _check(st, "pm_observe_dirichlet_sources")
         return out
 
     # -- replay / inspection ---------------------------------------------------------

@@ -43,6 +43,12 @@ struct pm_ctx {
     size_t nsteps_cap = 0;
     void *order = nullptr;
     size_t order_cap = 0;
+    void *integ_src = nullptr;  // Gaussian-source integrals [n_src][total], their partials
+    size_t integ_src_cap = 0;
+    void *part3 = nullptr;
+    size_t part3_cap = 0;
+    void *src_var = nullptr;
+    size_t src_var_cap = 0;
     void *fd_u = nullptr;  // finite differences: perturbed sets, their means and variances
     size_t fd_u_cap = 0;
     void *fd_m = nullptr;
@@ -130,13 +136,14 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 int to_field(const pm_field *f, FieldArg *out)
 {
     if (!f) return PM_EINVAL;
-    if (f->kind < PM_F_ZERO || f->kind > PM_F_LINEAR) return PM_EINVAL;
+    if (f->kind < PM_F_ZERO || f->kind > PM_F_COS_AXES) return PM_EINVAL;
     if (f->n_params < 0 || f->n_params > PM_FIELD_MAX_PARAMS) return PM_EINVAL;
     if (f->n_params > 0 && !f->params) return PM_EINVAL;
-    static const int need[] = {0, 1, 1, 4, 4, 1, 2, 3};
+    static const int need[] = {0, 1, 1, 4, 4, 1, 2, 3, 4, 2};
     const int n = f->n_params;
     if (n < need[f->kind]) return PM_EINVAL;
-    if ((f->kind == PM_F_FOURIER || f->kind == PM_F_GAUSS_PERIODIC) && (n % 4) != 0) return PM_EINVAL;
+    if ((f->kind == PM_F_FOURIER || f->kind == PM_F_GAUSS_PERIODIC || f->kind == PM_F_GAUSS) && (n % 4) != 0)
+        return PM_EINVAL;
     std::memset(out, 0, sizeof(*out));
     out->kind = f->kind;
     out->n = n;
@@ -496,7 +503,8 @@ template <typename T>
 int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, const FieldArg &f,
                            const FieldArg &g, const double *obs, int n_obs, double kappa, double dt,
                            int64_t np, uint64_t seed, int64_t max_steps, double *mean, double *var,
-                           double *tau_mean, double *tau_var, int64_t *n_capped, double *paths)
+                           double *tau_mean, double *tau_var, int64_t *n_capped, double *paths,
+                           int n_src = 0, const double *src = nullptr, double *src_mean = nullptr)
 {
     T *coef;
     int64_t cstride;
@@ -513,10 +521,16 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     if ((st = ensure(c, &c->part, &c->part_cap, cpo * n_obs * 3 * sizeof(double)))) return st;
     if ((st = ensure(c, &c->part2, &c->part2_cap, cpo * n_obs * 3 * sizeof(double)))) return st;
 
-    // zero, constant and linear sources run as f = p0 x + p1 y + p2 in the walk
+    // zero, constant and linear sources run as f = p0 x + p1 y + p2 in the walk;
+    // Gaussian sources (n_src > 0) integrate one integral per source
     int fk = 1;
     FieldArg fpoly{};
-    if (f.kind == PM_F_ZERO || f.kind == PM_F_CONST || f.kind == PM_F_LINEAR) {
+    if (n_src > 0) {
+        fk = 2;
+        if ((st = ensure(c, &c->integ_src, &c->integ_src_cap, (size_t)n_src * total * sizeof(double)))) return st;
+        if ((st = ensure(c, &c->part3, &c->part3_cap, cpo * n_obs * 3 * sizeof(double)))) return st;
+        if ((st = ensure(c, &c->src_var, &c->src_var_cap, (size_t)n_obs * sizeof(double)))) return st;
+    } else if (f.kind == PM_F_ZERO || f.kind == PM_F_CONST || f.kind == PM_F_LINEAR) {
         fk = 0;
         fpoly.kind = PM_F_LINEAR;
         fpoly.n = 3;
@@ -568,10 +582,14 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     a.nsteps = (double *)c->nsteps;
     a.capped = (unsigned char *)c->capped;
     a.queue = c->d_queue;
+    a.n_src = n_src;
+    for (int q = 0; q < n_src; ++q)
+        for (int e = 0; e < 3; ++e) a.src[q][e] = src[3 * q + e];
+    a.integ_src = (double *)c->integ_src;
 
     if (launch_zero_u64(c->d_queue, 1, c->stream) != hipSuccess) return PM_EDEVICE;
     PM_HIP(hipEventRecord(c->ev0, c->stream));
-    if (launch_dirichlet<T>(a, p->K, fk, c->dir_src, c->n_cu, c->dir_bpc, c->stream) != hipSuccess)
+    if (launch_dirichlet<T>(a, p->K, fk, c->dir_src, c->n_cu, c->dir_bpc, p->domain, c->stream) != hipSuccess)
         return PM_EDEVICE;
     PM_HIP(hipEventRecord(c->ev1, c->stream));
     c->timed = true;
@@ -605,6 +623,14 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     fa.var = tau_var;
     if (launch_finalize(fa, n_obs, c->stream) != hipSuccess) return PM_EDEVICE;
     if (launch_count_capped(a.capped, np, n_obs, n_capped, c->stream) != hipSuccess) return PM_EDEVICE;
+    for (int q = 0; q < n_src; ++q) {  // mean of each source integral per observation
+        const double *vals = (const double *)c->integ_src + (size_t)q * total;
+        if (launch_chunk_reduce(vals, np, n_obs, (double *)c->part3, c->d_flags, c->stream)) return PM_EDEVICE;
+        fa.partials = (const double *)c->part3;
+        fa.mean = src_mean + (size_t)q * n_obs;
+        fa.var = (double *)c->src_var;
+        if (launch_finalize(fa, n_obs, c->stream) != hipSuccess) return PM_EDEVICE;
+    }
     return PM_OK;
 }
 
@@ -679,7 +705,8 @@ void pm_destroy(pm_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     void *bufs[] = {c->d_flags, c->d_queue, c->coef, c->part, c->part2, c->pay, c->tau, c->capped,
-                    c->meta, c->states, c->exitp, c->integ, c->nsteps, c->order, c->fd_u, c->fd_m};
+                    c->meta, c->states, c->exitp, c->integ, c->nsteps, c->order, c->fd_u, c->fd_m,
+                    c->integ_src, c->part3, c->src_var};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->h_meta) (void)hipHostFree(c->h_meta);
@@ -713,7 +740,7 @@ int pm_problem_create(pm_ctx *c, pm_problem **out, int domain, int n_modes, cons
     if (!c || !out) return PM_EINVAL;
     *out = nullptr;
     if (c->closed) return PM_EINVAL;
-    if (domain != PM_TORUS && domain != PM_DISK) return PM_EINVAL;
+    if (domain != PM_TORUS && domain != PM_DISK && domain != PM_SQUARE) return PM_EINVAL;
     if (prec != PM_FP32 && prec != PM_FP64) return PM_EINVAL;
     if (n_modes < 0 || (n_modes > 0 && !k)) return PM_EINVAL;
     int K = 0;
@@ -906,7 +933,7 @@ int pm_observe_dirichlet(pm_ctx *c, const pm_problem *p, const double *u, const 
                          double *tau_mean, double *tau_var, int64_t *n_capped, double *paths)
 {
     if (!ctx_ok(c, p)) return PM_EINVAL;
-    if (p->domain != PM_DISK) return PM_EINVAL;
+    if (p->domain != PM_DISK && p->domain != PM_SQUARE) return PM_EINVAL;
     if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(obs) || bad_ptr(mean) || bad_ptr(var) ||
         bad_ptr(tau_mean) || bad_ptr(tau_var) || bad_ptr(n_capped))
         return PM_EINVAL;
@@ -922,6 +949,36 @@ int pm_observe_dirichlet(pm_ctx *c, const pm_problem *p, const double *u, const 
                                               mean, var, tau_mean, tau_var, n_capped, paths);
     return observe_dirichlet_impl<float>(c, p, u, ff, gg, obs, n_obs, kappa, dt, np, seed, max_steps, mean,
                                          var, tau_mean, tau_var, n_capped, paths);
+}
+
+int pm_observe_dirichlet_sources(pm_ctx *c, const pm_problem *p, const double *u, const pm_field *g,
+                                 const double *obs, int n_obs, double kappa, double dt, int64_t np,
+                                 uint64_t seed, int64_t max_steps, int n_src, const double *sources,
+                                 double *bnd_mean, double *bnd_var, double *src_mean, double *tau_mean,
+                                 double *tau_var, int64_t *n_capped)
+{
+    if (!ctx_ok(c, p)) return PM_EINVAL;
+    if (p->domain != PM_SQUARE) return PM_EUNSUPPORTED;
+    if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(obs) || bad_ptr(bnd_mean) || bad_ptr(bnd_var) ||
+        bad_ptr(src_mean) || bad_ptr(tau_mean) || bad_ptr(tau_var) || bad_ptr(n_capped) || !sources)
+        return PM_EINVAL;
+    if (n_src < 1 || n_src > PM_MAX_SOURCES) return PM_EINVAL;
+    for (int q = 0; q < 3 * n_src; ++q)
+        if (!std::isfinite(sources[q])) return PM_EINVAL;
+    FieldArg gg, zero{};
+    zero.kind = PM_F_ZERO;
+    if (to_field(g, &gg) != PM_OK) return PM_EINVAL;
+    if (n_obs < 1) return PM_EINVAL;
+    if (np < 1 || np > ((int64_t)1 << 32)) return PM_EINVAL;
+    if (!(std::isfinite(kappa) && kappa > 0.0) || !finite_pos(dt)) return PM_EINVAL;
+    if (max_steps < 1 || max_steps > ((int64_t)1 << 33)) return PM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    if (p->prec == PM_FP64)
+        return observe_dirichlet_impl<double>(c, p, u, zero, gg, obs, n_obs, kappa, dt, np, seed, max_steps,
+                                              bnd_mean, bnd_var, tau_mean, tau_var, n_capped, nullptr, n_src,
+                                              sources, src_mean);
+    return observe_dirichlet_impl<float>(c, p, u, zero, gg, obs, n_obs, kappa, dt, np, seed, max_steps, bnd_mean,
+                                         bnd_var, tau_mean, tau_var, n_capped, nullptr, n_src, sources, src_mean);
 }
 
 // Teacher-forced steps (Y) or velocities (V) through the matrix-core field.

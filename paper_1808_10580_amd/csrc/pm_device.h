@@ -322,6 +322,14 @@ __device__ inline double field_eval(const FieldArg &f, double x, double y)
         return exp(p[0] * x + p[1] * y);
     case PM_F_LINEAR:
         return p[0] * x + p[1] * y + p[2];
+    case PM_F_GAUSS:
+        for (int m = 0; m + 3 < f.n; m += 4) {
+            const double dx = x - p[m], dy = y - p[m + 1];
+            s += p[m + 3] * exp(-p[m + 2] * (dx * dx + dy * dy));
+        }
+        return s;
+    case PM_F_COS_AXES:
+        return p[0] * (cos(p[1] * x) + cos(p[1] * y));
     default:
         return __builtin_nan("");
     }

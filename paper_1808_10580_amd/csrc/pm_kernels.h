@@ -82,6 +82,10 @@ struct DirArgs {
     unsigned char *capped;
     unsigned long long *queue;
     const int *order;  // device [n_obs]: queue position -> observation (longest walks first)
+    // Gaussian sources (FK = 2): per particle int_0^tau exp(-w_s |X - c_s|^2) dt
+    int n_src;
+    double src[PM_MAX_SOURCES][3];  // (cx, cy, w)
+    double *integ_src;              // [n_src][total]
 };
 
 struct DirPayArgs {
@@ -211,7 +215,8 @@ hipError_t launch_fold(const FoldArgs &a, T *coef, int n_sets, hipStream_t st);
 template <typename T>
 hipError_t launch_time(const TimeArgs<T> &a, int K, int ppl, int src, int n_cu, int bpc, hipStream_t st);
 template <typename T>
-hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_cu, int bpc, hipStream_t st);
+hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_cu, int bpc, int domain,
+                            hipStream_t st);
 hipError_t launch_dir_payoff(const DirPayArgs &a, hipStream_t st);
 hipError_t launch_time_payoff(const PayArgs &a, hipStream_t st);
 hipError_t launch_chunk_reduce(const double *vals, int64_t np, int n_obs, double *partials,

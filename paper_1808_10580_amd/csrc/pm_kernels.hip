@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_fold(FoldArgs a, T *__restrict__ coef)
         psi[e] = acc;
     }
     __syncthreads();
-    const int nf = a.domain == PM_TORUS ? 2 : 3;
+    const int nf = a.domain == PM_DISK ? 3 : 2;  // the square uses the torus field
     const int R = a.row_stride;
     T *__restrict__ out = coef + (int64_t)b * a.coef_stride;
     const double tp = 6.283185307179586476925286766559;
@@ -358,11 +358,11 @@ __device__ __forceinline__ double source_at(const FieldArg &f, double x, double 
     else return field_eval(f, x, y);
 }
 
-template <typename T, int K, int FK, bool SC>
+template <typename T, int K, int FK, bool SC, int DOM>
 __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
 {
     constexpr int B = Geo<K>::B;
-    constexpr int R = Geo<K>::RD;
+    constexpr int R = DOM == PM_DISK ? Geo<K>::RD : Geo<K>::RT;
     constexpr int NC = B * R;
     __shared__ __align__(16) T lds[SC ? 4 : NC];
     if constexpr (!SC) {
@@ -377,6 +377,9 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
     x.set(0.0);
     y.set(0.0);
     double I = 0.0;
+    double Is[FK == 2 ? PM_MAX_SOURCES : 1];  // per-source integrals (FK = 2)
+#pragma unroll
+    for (int q = 0; q < (FK == 2 ? PM_MAX_SOURCES : 1); ++q) Is[q] = 0.0;
     int64_t n = 0, t = 0;
     uint32_t pi = 0, pj = 0;
 
@@ -386,6 +389,11 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
         a.integ[t] = I;
         a.nsteps[t] = (double)n;
         a.capped[t] = exited ? 0 : 1;
+        if constexpr (FK == 2) {
+#pragma unroll
+            for (int q = 0; q < PM_MAX_SOURCES; ++q)
+                if (q < a.n_src) a.integ_src[q * a.total + t] = Is[q];
+        }
         has = false;
     };
 
@@ -396,23 +404,56 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
         trig_basis<T, K>(ya, phy);
         T vx, vy;
         // coefficients re-read every step: scalar cache (SGPR operands) or LDS
-        if constexpr (SC) {
-            disk_velocity<T, K>(opaque_sgpr((cptr<T>)a.coef), phx, phy, xa, ya, vx, vy);
-        } else {
-            __asm__ volatile("" ::: "memory");
-            disk_velocity<T, K>((const T *)lds, phx, phy, xa, ya, vx, vy);
+        if constexpr (DOM == PM_DISK) {
+            if constexpr (SC) {
+                disk_velocity<T, K>(opaque_sgpr((cptr<T>)a.coef), phx, phy, xa, ya, vx, vy);
+            } else {
+                __asm__ volatile("" ::: "memory");
+                disk_velocity<T, K>((const T *)lds, phx, phy, xa, ya, vx, vy);
+            }
+        } else {  // the square: the periodic Fourier field, no cutoff
+            const T(&px)[1][B] = reinterpret_cast<const T(&)[1][B]>(phx);
+            const T(&py)[1][B] = reinterpret_cast<const T(&)[1][B]>(phy);
+            T ax[1], ay[1];
+            if constexpr (SC) {
+                torus_velocity<T, K, 1>(opaque_sgpr((cptr<T>)a.coef), px, py, ax, ay);
+            } else {
+                __asm__ volatile("" ::: "memory");
+                torus_velocity<T, K, 1>((const T *)lds, px, py, ax, ay);
+            }
+            vx = ax[0];
+            vy = ay[0];
         }
         Coord<T> nx = x, ny = y;
         nx.advance(vx + a.v0x, z0, a.sc);
         ny.advance(vy + a.v0y, z1, a.sc);
         if (has) {
-            I += source_at<FK>(a.f, x.value(), y.value()) * a.dtd;  // left point
+            const double xd = x.value(), yd = y.value();
+            if constexpr (FK == 2) {  // left point, one integral per Gaussian source
+#pragma unroll
+                for (int q = 0; q < PM_MAX_SOURCES; ++q) {
+                    if (q < a.n_src) {
+                        const double dx = xd - a.src[q][0], dy = yd - a.src[q][1];
+                        Is[q] += exp(-a.src[q][2] * (dx * dx + dy * dy)) * a.dtd;
+                    }
+                }
+            } else {
+                I += source_at<FK>(a.f, xd, yd) * a.dtd;  // left point
+            }
             n += 1;
             const double nxd = nx.value(), nyd = ny.value();
-            const double r2 = nxd * nxd + nyd * nyd;
-            if (r2 >= 1.0) {
-                const double r = sqrt(r2);
-                finish(nxd / r, nyd / r, true);
+            bool out;
+            if constexpr (DOM == PM_DISK) out = nxd * nxd + nyd * nyd >= 1.0;
+            else out = !(nxd > 0.0 && nxd < 1.0 && nyd > 0.0 && nyd < 1.0);
+            if (out) {
+                // exit point: the nearest boundary point (radial projection
+                // onto the circle; clamping onto the square)
+                if constexpr (DOM == PM_DISK) {
+                    const double r = sqrt(nxd * nxd + nyd * nyd);
+                    finish(nxd / r, nyd / r, true);
+                } else {
+                    finish(fmin(fmax(nxd, 0.0), 1.0), fmin(fmax(nyd, 0.0), 1.0), true);
+                }
             } else if (n >= a.max_steps) {
                 finish(nxd, nyd, false);
             } else {
@@ -441,6 +482,8 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
                     x.set(a.obs[2 * pj]);
                     y.set(a.obs[2 * pj + 1]);
                     I = 0.0;
+#pragma unroll
+                    for (int q = 0; q < (FK == 2 ? PM_MAX_SOURCES : 1); ++q) Is[q] = 0.0;
                     n = 0;
                     has = true;
                 } else {
@@ -665,7 +708,7 @@ __device__ __forceinline__ void velocity_at(const T *__restrict__ C, int domain,
     T phx[2 * K + 1], phy[2 * K + 1];
     trig_basis<T, K>(x, phx);
     trig_basis<T, K>(y, phy);
-    if (domain == PM_TORUS) {
+    if (domain != PM_DISK) {  // torus, and the square (the periodic field evaluated on it)
         const T(&px)[1][2 * K + 1] = reinterpret_cast<const T(&)[1][2 * K + 1]>(phx);
         const T(&py)[1][2 * K + 1] = reinterpret_cast<const T(&)[1][2 * K + 1]>(phy);
         T ax[1], ay[1];
@@ -760,7 +803,7 @@ static hipError_t dispatch_k(int K, F &&f)
 int row_stride(int domain, int K)
 {
     const int B = 2 * K + 1;
-    const int nf = domain == PM_TORUS ? 2 : 3;
+    const int nf = domain == PM_DISK ? 3 : 2;
     return ((nf * B + 3) / 4) * 4;
 }
 
@@ -821,12 +864,21 @@ template hipError_t launch_time<float>(const TimeArgs<float> &, int, int, int, i
 template hipError_t launch_time<double>(const TimeArgs<double> &, int, int, int, int, int, hipStream_t);
 
 template <typename T>
-hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_cu, int bpc, hipStream_t st)
+hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_cu, int bpc, int domain,
+                            hipStream_t st)
 {
     return dispatch_k(K, [&](auto kc) -> hipError_t {
         constexpr int KK = decltype(kc)::value;
-        auto kern = src == PM_COEF_SCALAR ? (fk == 0 ? k_dirichlet<T, KK, 0, true> : k_dirichlet<T, KK, 1, true>)
-                                          : (fk == 0 ? k_dirichlet<T, KK, 0, false> : k_dirichlet<T, KK, 1, false>);
+        // disk: both coefficient sources; square: scalar cache only, plus the
+        // Gaussian-source integrals (fk = 2)
+        void (*kern)(const DirArgs<T>);
+        if (domain == PM_DISK)
+            kern = src == PM_COEF_SCALAR
+                       ? (fk == 0 ? k_dirichlet<T, KK, 0, true, PM_DISK> : k_dirichlet<T, KK, 1, true, PM_DISK>)
+                       : (fk == 0 ? k_dirichlet<T, KK, 0, false, PM_DISK> : k_dirichlet<T, KK, 1, false, PM_DISK>);
+        else
+            kern = fk == 0 ? k_dirichlet<T, KK, 0, true, PM_SQUARE>
+                           : (fk == 1 ? k_dirichlet<T, KK, 1, true, PM_SQUARE> : k_dirichlet<T, KK, 2, true, PM_SQUARE>);
         int per_cu = 0;
         hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
         if (err != hipSuccess) return err;
@@ -840,8 +892,8 @@ hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_c
         return hipGetLastError();
     });
 }
-template hipError_t launch_dirichlet<float>(const DirArgs<float> &, int, int, int, int, int, hipStream_t);
-template hipError_t launch_dirichlet<double>(const DirArgs<double> &, int, int, int, int, int, hipStream_t);
+template hipError_t launch_dirichlet<float>(const DirArgs<float> &, int, int, int, int, int, int, hipStream_t);
+template hipError_t launch_dirichlet<double>(const DirArgs<double> &, int, int, int, int, int, int, hipStream_t);
 
 hipError_t launch_dir_payoff(const DirPayArgs &a, hipStream_t st)
 {
