@@ -259,9 +259,11 @@ __device__ __forceinline__ void hk_velocity_block(const unsigned char *__restric
             o[5] = rx.c[3];
             o[6] = rx.s[3];
             o[7] = rx.c[4];
+            // entries past B meet zero coefficient rows, so their (finite)
+            // values do not matter and need no masking
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const float v = (i0 + e < B) ? o[e] * (float)(1 << HK_BASIS_SHIFT) : 0.f;
+                const float v = o[e] * (float)(1 << HK_BASIS_SHIFT);
                 const _Float16 hi = (_Float16)v;
                 bh[kt][rb][e] = hi;
                 bl[kt][rb][e] = (_Float16)(v - (float)hi);
@@ -315,11 +317,11 @@ __device__ __forceinline__ void hk_velocity_block(const unsigned char *__restric
             f4[1] = ry[rb].c[1];
             f4[2] = ry[rb].s[1];
             f4[3] = ry[rb].c[2];
+            // rows j >= B of D are exact zeros (zero coefficient columns)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float fr = (j0 + r < B) ? f4[r] : 0.f;
-                ax[rb] = __builtin_fmaf(dx[rb][r], fr, ax[rb]);
-                ay[rb] = __builtin_fmaf(dy[rb][r], fr, ay[rb]);
+                ax[rb] = __builtin_fmaf(dx[rb][r], f4[r], ax[rb]);
+                ay[rb] = __builtin_fmaf(dy[rb][r], f4[r], ay[rb]);
             }
         }
         __builtin_amdgcn_s_waitcnt(0);  // stage nt+1 has landed in LDS
