@@ -542,26 +542,10 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
         }
     }
 
-    // Deal the walks with the longest expected exit time first: without flow
-    // E tau = (1 - |x|^2) / (4 kappa), so points nearer the centre go first and
-    // the heavy tail of the last walks comes from short-expected points.
+    // Deal the walks with the longest expected exit time first (points nearest
+    // the centre first; computed on the device, no synchronisation)
     if ((st = ensure(c, &c->order, &c->order_cap, (size_t)n_obs * sizeof(int)))) return st;
-    {
-        std::vector<double> ho(2 * (size_t)n_obs);
-        if (hipMemcpyAsync(ho.data(), obs, ho.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-            hipStreamSynchronize(c->stream) != hipSuccess)
-            return PM_EDEVICE;
-        std::vector<int> ord(n_obs);
-        for (int j = 0; j < n_obs; ++j) ord[j] = j;
-        std::stable_sort(ord.begin(), ord.end(), [&](int p, int q) {
-            return ho[2 * p] * ho[2 * p] + ho[2 * p + 1] * ho[2 * p + 1] <
-                   ho[2 * q] * ho[2 * q] + ho[2 * q + 1] * ho[2 * q + 1];
-        });
-        if (hipMemcpyAsync(c->order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice, c->stream) !=
-                hipSuccess ||
-            hipStreamSynchronize(c->stream) != hipSuccess)
-            return PM_EDEVICE;
-    }
+    if (launch_walk_order(obs, n_obs, p->domain, (int *)c->order, c->stream) != hipSuccess) return PM_EDEVICE;
 
     DirArgs<T> a{};
     a.coef = coef;

@@ -225,6 +225,7 @@ hipError_t launch_finalize(const FinalArgs &a, int n_groups, hipStream_t st);
 hipError_t launch_count_capped(const unsigned char *capped, int64_t np, int n_obs, int64_t *out,
                                hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
+hipError_t launch_walk_order(const double *obs, int n_obs, int domain, int *order, hipStream_t st);
 // Central finite differences of G: parameter sets u +- h e_k and the
 // Jacobian from their means.
 hipError_t launch_fd_sets(const double *u, int n_coef, double h, double *U, hipStream_t st);

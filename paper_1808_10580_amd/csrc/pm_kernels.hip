@@ -656,6 +656,42 @@ __global__ void k_zero_u64(unsigned long long *p, int n)
 }
 
 // ---------------------------------------------------------------------------
+// Order of the Dirichlet walk's observation points: ascending distance from
+// the centre, ties by index (order[rank] = point).  Without flow the expected
+// exit time from the unit disk, (1 - |x|^2) / (4 kappa), falls with |x|, so
+// the longest walks are dealt first.  One thread per point counts the points
+// that precede it.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_walk_order(const double *__restrict__ obs, int n_obs, int domain,
+                                                    int *__restrict__ order)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_obs) return;
+    // disk: distance from the origin; square: from its centre (1/2, 1/2)
+    const double c = domain == PM_DISK ? 0.0 : 0.5;
+    // NaN keys count as +inf, so (key, index) is a strict total order and the
+    // ranks form a permutation whatever the input holds
+    auto key = [&](int q) {
+        const double dx = obs[2 * q] - c, dy = obs[2 * q + 1] - c;
+        const double k = dx * dx + dy * dy;
+        return k == k ? k : __builtin_inf();
+    };
+    const double ki = key(i);
+    int rank = 0;
+    for (int q = 0; q < n_obs; ++q) {
+        const double kq = key(q);
+        rank += (kq < ki || (kq == ki && q < i)) ? 1 : 0;
+    }
+    order[rank] = i;
+}
+
+hipError_t launch_walk_order(const double *obs, int n_obs, int domain, int *order, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_walk_order, dim3((n_obs + 255) / 256), dim3(256), 0, st, obs, n_obs, domain, order);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Finite differences: set 2k is u + h e_k, set 2k+1 is u - h e_k; the
 // Jacobian divides the difference of their means by the difference of the
 // coefficients actually evaluated (u_k + h) - (u_k - h).
