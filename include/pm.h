@@ -277,6 +277,18 @@ int pm_set_blocks_per_cu(pm_ctx *ctx, int blocks_per_cu);
  * do not depend on it. */
 int pm_set_dirichlet_blocks_per_cu(pm_ctx *ctx, int blocks_per_cu);
 
+/* Compaction of the Dirichlet walk's tail (default off: dump_below 0,
+ * launches 8).  Exit times are heavy-tailed, so the last walks run in waves
+ * with few live lanes.  Once no fresh particle is left, a wave whose live
+ * lanes drop below dump_below (and that has run at least 2,048 steps in its
+ * launch) saves its walkers to a pool and ends; up to `launches` follow-up
+ * launches deal the pool densely, the last running every walker to its exit.
+ * Paths, results and their order are unchanged bit for bit.  On the disk
+ * workload the tail is bound by the longest walks' own step latency, not by
+ * sparse waves, so this measured no faster there; it is kept for workloads
+ * whose tails are wide rather than long. */
+int pm_set_dirichlet_compaction(pm_ctx *ctx, int dump_below, int launches);
+
 /* Autotuner for the time kernel (Algorithm 1): times every particles-per-lane
  * and coefficient-source variant on a probe of n_probe_steps steps with the
  * given particle count and stores the fastest for this problem's K in the

@@ -67,6 +67,10 @@ struct pm_ctx {
     int bpc = 0;  // persistent blocks per CU (0 = occupancy limit)
     int dir_src = PM_COEF_SCALAR;  // Dirichlet kernel coefficient source
     int dir_bpc = 2;               // Dirichlet persistent blocks per CU (0 = occupancy)
+    int dir_dump = 0;              // Dirichlet compaction (off): save waves with fewer live lanes
+    int dir_launches = 8;          // ... over this many follow-up launches
+    void *pool = nullptr;          // compaction pools: counters, states, indices
+    size_t pool_cap = 0;
     int tune_ppl[PM_MAX_K + 1] = {0};  // autotuned choice per harmonic count K
     int tune_src[PM_MAX_K + 1] = {0};
     bool capturing = false;  // recording a graph: no timing events, no host waits
@@ -571,10 +575,44 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
         for (int e = 0; e < 3; ++e) a.src[q][e] = src[3 * q + e];
     a.integ_src = (double *)c->integ_src;
 
+    // Compaction pools (two, used alternately): walkers saved by one launch
+    // are dealt densely by the next; the last launch runs every walker out.
+    const int n_follow = c->dir_dump > 0 ? c->dir_launches : 0;
+    DirPool pools[2] = {};
+    if (n_follow > 0) {
+        const int64_t cap = std::min<int64_t>(total, dirichlet_max_lanes(c->n_cu));
+        const size_t st_bytes = (size_t)cap * DIR_POOL_WORDS * sizeof(double);
+        const size_t ij_bytes = (size_t)cap * 2 * sizeof(uint32_t);
+        const size_t bytes = 4 * sizeof(unsigned long long) + 2 * (st_bytes + ij_bytes);
+        if ((st = ensure(c, &c->pool, &c->pool_cap, bytes))) return st;
+        char *base = (char *)c->pool;
+        for (int q = 0; q < 2; ++q) {
+            pools[q].count = (unsigned long long *)base + 2 * q;
+            pools[q].head = (unsigned long long *)base + 2 * q + 1;
+            pools[q].st = (double *)(base + 4 * sizeof(unsigned long long) + q * st_bytes);
+            pools[q].ij = (uint32_t *)(base + 4 * sizeof(unsigned long long) + 2 * st_bytes + q * ij_bytes);
+        }
+        if (launch_zero_u64((unsigned long long *)base, 4, c->stream) != hipSuccess) return PM_EDEVICE;
+    }
+    a.min_iters = 1024;
+
     if (launch_zero_u64(c->d_queue, 1, c->stream) != hipSuccess) return PM_EDEVICE;
     PM_HIP(hipEventRecord(c->ev0, c->stream));
+    a.mode = 0;
+    a.dump_below = n_follow > 0 ? c->dir_dump : 0;
+    a.pout = pools[0];
     if (launch_dirichlet<T>(a, p->K, fk, c->dir_src, c->n_cu, c->dir_bpc, p->domain, c->stream) != hipSuccess)
         return PM_EDEVICE;
+    for (int r = 1; r <= n_follow; ++r) {
+        a.mode = 1;
+        a.pin = pools[(r - 1) & 1];
+        a.pout = pools[r & 1];
+        a.dump_below = r < n_follow ? c->dir_dump : 0;
+        if (launch_pool_reset(a.pin.head, a.pout.count, c->stream) != hipSuccess) return PM_EDEVICE;
+        if (launch_dirichlet<T>(a, p->K, fk, c->dir_src, c->n_cu, c->dir_bpc, p->domain, c->stream) !=
+            hipSuccess)
+            return PM_EDEVICE;
+    }
     PM_HIP(hipEventRecord(c->ev1, c->stream));
     c->timed = true;
     c->last_steps = -1.0;  // counted by the caller from the exit steps
@@ -690,7 +728,7 @@ void pm_destroy(pm_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     void *bufs[] = {c->d_flags, c->d_queue, c->coef, c->part, c->part2, c->pay, c->tau, c->capped,
                     c->meta, c->states, c->exitp, c->integ, c->nsteps, c->order, c->fd_u, c->fd_m,
-                    c->integ_src, c->part3, c->src_var};
+                    c->integ_src, c->part3, c->src_var, c->pool};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->h_meta) (void)hipHostFree(c->h_meta);
@@ -1100,6 +1138,14 @@ int pm_set_dirichlet_blocks_per_cu(pm_ctx *c, int bpc)
 {
     if (!c || c->closed || bpc < 0) return PM_EINVAL;
     c->dir_bpc = bpc;
+    return PM_OK;
+}
+
+int pm_set_dirichlet_compaction(pm_ctx *c, int dump_below, int launches)
+{
+    if (!c || c->closed || dump_below < 0 || dump_below > 64 || launches < 0 || launches > 64) return PM_EINVAL;
+    c->dir_dump = dump_below;
+    c->dir_launches = launches;
     return PM_OK;
 }
 

@@ -153,6 +153,12 @@ struct Coord<double> {
         v = __builtin_fma(c.sq, z, v);
     }
     __device__ __forceinline__ void wrap() { v -= floor(v); }
+    __device__ __forceinline__ void save(double &a, double &b) const
+    {
+        a = v;
+        b = 0.0;
+    }
+    __device__ __forceinline__ void load(double a, double) { v = a; }
 };
 
 template <>
@@ -178,6 +184,17 @@ struct Coord<float> {
         lo = e - (hi - s);
     }
     __device__ __forceinline__ void wrap() { hi -= __builtin_rintf(hi); }
+    // exact round trip through two doubles
+    __device__ __forceinline__ void save(double &a, double &b) const
+    {
+        a = (double)hi;
+        b = (double)lo;
+    }
+    __device__ __forceinline__ void load(double a, double b)
+    {
+        hi = (float)a;
+        lo = (float)b;
+    }
 };
 
 // Pointer into the constant address space: uniform loads through it become

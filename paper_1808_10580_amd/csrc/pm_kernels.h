@@ -63,6 +63,15 @@ struct PayArgs {
     unsigned *flags;
 };
 
+// Walkers saved between the launches of a compacted Dirichlet walk.
+constexpr int DIR_POOL_WORDS = 6 + PM_MAX_SOURCES;  // x hi, x lo, y hi, y lo, int f, steps, source integrals
+struct DirPool {
+    unsigned long long *count;  // walkers stored
+    unsigned long long *head;   // next walker to deal when the pool is the input
+    double *st;                 // [cap][DIR_POOL_WORDS]
+    uint32_t *ij;               // [cap][2] particle and observation index
+};
+
 template <typename T>
 struct DirArgs {
     const T *coef;
@@ -86,6 +95,14 @@ struct DirArgs {
     int n_src;
     double src[PM_MAX_SOURCES][3];  // (cx, cy, w)
     double *integ_src;              // [n_src][total]
+    // Compaction: mode 0 deals fresh particles, mode 1 the walkers of pin.
+    // Once its input is exhausted, a wave with 1..dump_below-1 live lanes that
+    // has run at least min_iters iterations in this launch saves its walkers
+    // to pout and exits (dump_below = 0: run every walker to its exit).
+    int mode;
+    int dump_below;
+    int min_iters;
+    DirPool pin, pout;
 };
 
 struct DirPayArgs {
@@ -226,6 +243,8 @@ hipError_t launch_count_capped(const unsigned char *capped, int64_t np, int n_ob
                                hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
 hipError_t launch_walk_order(const double *obs, int n_obs, int domain, int *order, hipStream_t st);
+hipError_t launch_pool_reset(unsigned long long *in_head, unsigned long long *out_count, hipStream_t st);
+int64_t dirichlet_max_lanes(int n_cu);  // resident lanes of the largest Dirichlet grid
 // Central finite differences of G: parameter sets u +- h e_k and the
 // Jacobian from their means.
 hipError_t launch_fd_sets(const double *u, int n_coef, double h, double *U, hipStream_t st);

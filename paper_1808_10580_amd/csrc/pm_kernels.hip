@@ -463,35 +463,79 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
         }
     };
 
+    // input: fresh particles (mode 0) or saved walkers (mode 1)
+    unsigned long long *const qhead = a.mode ? a.pin.head : a.queue;
+    const int64_t limit = a.mode ? (int64_t)uniform64((int64_t)*a.pin.count) : a.total;
+    int iters = 0;
     for (;;) {
         const bool need = !has && !done;
         const unsigned long long m = __ballot(need);
         if (m) {
             const int first = __ffsll((long long)m) - 1;
             unsigned long long base = 0;
-            if (lane == first) base = atomicAdd(a.queue, (unsigned long long)__popcll(m));
+            if (lane == first) base = atomicAdd(qhead, (unsigned long long)__popcll(m));
             base = __shfl(base, first);
             if (need) {
                 const int rank = __popcll(m & ((1ull << lane) - 1ull));
                 const int64_t tt = (int64_t)base + rank;
-                if (tt < a.total) {
-                    const int64_t jq = tt / a.np;
-                    pj = (uint32_t)a.order[jq];
-                    pi = (uint32_t)(tt - jq * a.np);
-                    t = (int64_t)pj * a.np + pi;
-                    x.set(a.obs[2 * pj]);
-                    y.set(a.obs[2 * pj + 1]);
-                    I = 0.0;
+                if (tt < limit) {
+                    if (a.mode == 0) {
+                        const int64_t jq = tt / a.np;
+                        pj = (uint32_t)a.order[jq];
+                        pi = (uint32_t)(tt - jq * a.np);
+                        x.set(a.obs[2 * pj]);
+                        y.set(a.obs[2 * pj + 1]);
+                        I = 0.0;
 #pragma unroll
-                    for (int q = 0; q < (FK == 2 ? PM_MAX_SOURCES : 1); ++q) Is[q] = 0.0;
-                    n = 0;
+                        for (int q = 0; q < (FK == 2 ? PM_MAX_SOURCES : 1); ++q) Is[q] = 0.0;
+                        n = 0;
+                    } else {  // resume a saved walker where it stopped (an even step count)
+                        const double *S = a.pin.st + tt * DIR_POOL_WORDS;
+                        x.load(S[0], S[1]);
+                        y.load(S[2], S[3]);
+                        I = S[4];
+                        n = (int64_t)S[5];
+                        if constexpr (FK == 2) {
+#pragma unroll
+                            for (int q = 0; q < PM_MAX_SOURCES; ++q) Is[q] = S[6 + q];
+                        }
+                        pi = a.pin.ij[2 * tt];
+                        pj = a.pin.ij[2 * tt + 1];
+                    }
+                    t = (int64_t)pj * a.np + pi;
                     has = true;
                 } else {
                     done = true;
                 }
             }
         }
-        if (__ballot(has) == 0) break;
+        const unsigned long long hm = __ballot(has);
+        if (hm == 0) break;
+        // compaction: the input is exhausted for this wave and too few lanes
+        // are still walking; hand the walkers to the next launch
+        if (a.dump_below > 0 && iters >= a.min_iters && __ballot(done) != 0 &&
+            __popcll(hm) < a.dump_below) {
+            const int first = __ffsll((long long)hm) - 1;
+            unsigned long long base = 0;
+            if (lane == first) base = atomicAdd(a.pout.count, (unsigned long long)__popcll(hm));
+            base = __shfl(base, first);
+            if (has) {
+                const int64_t slot = (int64_t)base + __popcll(hm & ((1ull << lane) - 1ull));
+                double *S = a.pout.st + slot * DIR_POOL_WORDS;
+                x.save(S[0], S[1]);
+                y.save(S[2], S[3]);
+                S[4] = I;
+                S[5] = (double)n;
+                if constexpr (FK == 2) {
+#pragma unroll
+                    for (int q = 0; q < PM_MAX_SOURCES; ++q) S[6 + q] = Is[q];
+                }
+                a.pout.ij[2 * slot] = pi;
+                a.pout.ij[2 * slot + 1] = pj;
+            }
+            break;
+        }
+        ++iters;
         const U4 w = philox4x32_10((uint32_t)(n >> 1), pi, pj, 0u, k0, k1);
         T z0, z1, z2, z3;
         box_muller(w.x, w.y, z0, z1);
@@ -684,6 +728,23 @@ __global__ __launch_bounds__(256) void k_walk_order(const double *__restrict__ o
     }
     order[rank] = i;
 }
+
+__global__ void k_pool_reset(unsigned long long *in_head, unsigned long long *out_count)
+{
+    if (threadIdx.x == 0) {
+        *in_head = 0ull;
+        *out_count = 0ull;
+    }
+}
+
+hipError_t launch_pool_reset(unsigned long long *in_head, unsigned long long *out_count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pool_reset, dim3(1), dim3(64), 0, st, in_head, out_count);
+    return hipGetLastError();
+}
+
+// At most 8 blocks of 256 threads per CU are resident (32 waves per CU).
+int64_t dirichlet_max_lanes(int n_cu) { return (int64_t)n_cu * 8 * 256; }
 
 hipError_t launch_walk_order(const double *obs, int n_obs, int domain, int *order, hipStream_t st)
 {
@@ -919,6 +980,7 @@ hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_c
         hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
         if (err != hipSuccess) return err;
         if (per_cu < 1) per_cu = 1;
+        if (per_cu > 8) per_cu = 8;  // the compaction pools hold dirichlet_max_lanes() walkers
         if (bpc > 0 && bpc < per_cu) per_cu = bpc;
         int64_t blocks = (int64_t)per_cu * n_cu;
         const int64_t need = (a.total + 255) / 256;

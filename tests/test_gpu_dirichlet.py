@@ -185,3 +185,38 @@ def test_coefficient_sources_are_bitwise_identical(pm, ctx):
         res.append(np_(out["paths"]).copy())
     ctx.set_dirichlet_source(1)
     assert np.array_equal(res[0], res[1])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("dump,launches", [(32, 8), (64, 3), (8, 20)])
+def test_compaction_is_bitwise_neutral(pm, ctx, prec, dump, launches):
+    """Saving tail walkers between launches and resuming them elsewhere changes
+    nothing: every path, payoff, exit step and statistic is identical."""
+    wl = W.dirichlet_main(n_particles=2000, prec=prec)
+    prob = pm.Problem(ctx, "disk", wl.modes, prec=prec)
+    res = []
+    for setting in ((0, 0), (dump, launches)):
+        ctx.set_dirichlet_compaction(*setting)
+        out = prob.observe_dirichlet(wl.u, wl.f, wl.g, wl.obs, wl.kappa, wl.dt, wl.n_particles, wl.seed,
+                                     wl.max_steps, paths=True)
+        assert ctx.sync() == pm.PM_OK
+        res.append({k: np_(v).copy() for k, v in out.items()})
+    ctx.set_dirichlet_compaction(0, 8)  # the default
+    for k in res[0]:
+        assert np.array_equal(res[0][k], res[1][k]), k
+    prob.close()
+
+
+def test_compaction_keeps_source_integrals(pm, ctx):
+    wl = W.bvp_square(n_particles=3000)
+    prob = pm.Problem(ctx, "square", wl.modes, v0=wl.v0, prec="fp32")
+    res = []
+    for setting in ((0, 0), (48, 6)):
+        ctx.set_dirichlet_compaction(*setting)
+        out = prob.observe_dirichlet_sources(wl.u, wl.g, wl.obs, wl.kappa, wl.dt, wl.n_particles, wl.seed,
+                                             wl.max_steps, wl.extra["sources"])
+        res.append({k: np_(v).copy() for k, v in out.items()})
+    ctx.set_dirichlet_compaction(0, 8)  # the default
+    for k in res[0]:
+        assert np.array_equal(res[0][k], res[1][k]), k
+    prob.close()
