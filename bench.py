@@ -34,8 +34,8 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 # of known size (the copy kernel reads FETCH_SIZE at 0.5 and WRITE_SIZE at 1.0
 # of the bytes moved).  Valid only for the kernel sources they were taken on:
 # reported when the sources still hash to KERNEL_SOURCES_SHA256, else null.
-COUNTER_TRAFFIC_BYTES = 79_671_072  # FETCH 161.5 KiB x 2 + WRITE 77,480.8 KiB x 1
-KERNEL_SOURCES_SHA256 = "669e917095df8d6a9398fc5ff3898cc3139e7403dd0cb951408223a9a24cd211"
+COUNTER_TRAFFIC_BYTES = 79_674_656  # FETCH 163.25 KiB x 2 + WRITE 77,480.78 KiB x 1
+KERNEL_SOURCES_SHA256 = "07d7dbb6588befae6b41407d7750db1ba9c289cf31081fd4d6e49d1a8c6c8f6e"
 KERNEL_SOURCES = ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
                   "paper_1808_10580_amd/csrc/pm_kernels.hip")
 
@@ -225,7 +225,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-particles", type=int, default=400,
+    ap.add_argument("--cpu-particles", type=int, default=2400,
                     help="particles per point in the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ppl", type=int, default=0, help="particles per lane (0 = library default)")
