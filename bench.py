@@ -11,8 +11,10 @@ each step ends when the 49 means are back on the host (as an MCMC step needs).
 
 Prints one JSON line:
   value            particle-steps/s over the K timed steps (wall clock)
-  roofline         the time kernel's FP32 FLOP rate from HIP events on its
-                   stream against the chip's FP32 vector peak
+  roofline         the time kernel's algorithmic FP32 FLOP rate from HIP
+                   events on its stream against the chip's FP32 vector peak
+                   (with the matrix-core engine also its issued FP16 matrix
+                   FLOP rate against the dense FP16 peak)
   cpu_baseline     the FP64 CPU oracle on a bounded sample of the same workload
 """
 from __future__ import annotations
@@ -33,20 +35,61 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 # FETCH_SIZE and WRITE_SIZE counters scaled by what they read for a plain copy
 # of known size (the copy kernel reads FETCH_SIZE at 0.5 and WRITE_SIZE at 1.0
 # of the bytes moved).  Valid only for the kernel sources they were taken on:
-# reported when the sources still hash to KERNEL_SOURCES_SHA256, else null.
-COUNTER_TRAFFIC_BYTES = 79_674_656  # FETCH 163.25 KiB x 2 + WRITE 77,480.78 KiB x 1
-KERNEL_SOURCES_SHA256 = "07d7dbb6588befae6b41407d7750db1ba9c289cf31081fd4d6e49d1a8c6c8f6e"
-KERNEL_SOURCES = ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
-                  "paper_1808_10580_amd/csrc/pm_kernels.hip")
+# reported when the sources still hash to the recorded value, else null.
+# Per velocity engine: (bytes per launch, SHA-256 of the kernel's sources).
+COUNTER_TRAFFIC = {
+    # FETCH 163.25 KiB x 2 + WRITE 77,480.78 KiB x 1
+    "valu": (79_674_656, "07d7dbb6588befae6b41407d7750db1ba9c289cf31081fd4d6e49d1a8c6c8f6e"),
+    "mfma": (None, None),
+}
+KERNEL_SOURCES = {
+    "valu": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
+             "paper_1808_10580_amd/csrc/pm_kernels.hip"),
+    "mfma": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
+             "paper_1808_10580_amd/csrc/pm_mx.h", "paper_1808_10580_amd/csrc/pm_mx.hip"),
+}
+# Matrix-core FLOPs issued per particle-step by the small-K engine: per 64
+# particles two 32-column blocks x three v_mfma_f32_32x32x16_f16 (32 x 32 x 16
+# multiply-adds each), padding included.
+MX_ISSUED_FLOP_PER_PARTICLE_STEP = 2 * 3 * 2 * 32 * 32 * 16 // 64
+PEAK_FP16_DENSE_TFLOPS = 2500.0
 
 
-def kernel_sources_sha256() -> str:
+def kernel_sources_sha256(engine: str = "valu") -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[engine]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def counter_traffic(engine: str):
+    nbytes, sha = COUNTER_TRAFFIC[engine]
+    if nbytes is None or kernel_sources_sha256(engine) != sha:
+        return None
+    return nbytes
+
+
+def engine_in_use(pm, engine_arg: str, K: int) -> str:
+    """The velocity engine the library runs for an FP32 torus problem."""
+    if engine_arg == "valu" or not (1 <= K <= pm.MAX_K_MX):
+        return "valu"
+    return "mfma"
+
+
+def kernel_roofline(engine: str, K: int, fl: int, steps: float, kern_s: float, traffic):
+    achieved = fl * steps / kern_s / 1e12
+    rl = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+          "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "traffic_unit": "bytes per launch",
+          "kernel": "k_time_mx<%d>" % K if engine == "mfma" else "k_time<float,%d>" % K,
+          "kernel_ms": round(kern_s * 1e3, 3), "flop_per_particle_step": fl, "engine": engine}
+    if engine == "mfma":
+        issued = MX_ISSUED_FLOP_PER_PARTICLE_STEP * steps / kern_s / 1e12
+        rl["matrix_cores"] = {"contraction": "split FP16 x3 (hi*hi + hi*lo + lo*hi), FP32 accumulate",
+                              "issued_tflops": round(issued, 2), "peak_fp16_dense": PEAK_FP16_DENSE_TFLOPS,
+                              "frac": round(issued / PEAK_FP16_DENSE_TFLOPS, 4)}
+    return rl
 
 
 def flops_per_particle_step(K: int) -> int:
@@ -129,6 +172,7 @@ def bench_other(args):
 
     dev = torch.device("cuda", 0)
     ctx = pm.Context(0)
+    ctx.set_time_engine(args.engine)
     name = args.workload
     cpu = None
     if name == "torus-k80-turbulent":
@@ -185,17 +229,18 @@ def bench_other(args):
         prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
         U = torch.tensor(wl.u, dtype=torch.float64, device=dev)
         obs = torch.tensor(wl.obs, dtype=torch.float64, device=dev)
-        prob.autotune_time(U[0], obs, wl.kappa, wl.dt, 100_000, 1, n_probe_steps=100)
+        K = int(abs(wl.modes).max())
+        engine = engine_in_use(pm, args.engine, K)
+        if engine == "valu":
+            prob.autotune_time(U[0], obs, wl.kappa, wl.dt, 100_000, 1, n_probe_steps=100)
 
         def run():
             m, _ = prob.observe_time_batch(U, wl.n_particles, wl.seed, obs, wl.kappa, wl.T, wl.dt)
             m.cpu()
             if ctx.sync() != pm.PM_OK:
                 raise pm.PMError(ctx.sync(), "forward map")
-        K = int(abs(wl.modes).max())
         fl = flops_per_particle_step(K)
-        rl = {"bound": "alu", "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "kernel": f"k_time<float,{K}>",
-              "flop_per_particle_step": fl}
+        rl = {"engine": engine}
         desc = ("torus-k6-batch: 512 pCN proposals (beta 0.2) of the |k|_inf<=6 problem in one launch, per-set "
                 "particle counts log-uniform in [1e3, 1e5], 49 points, 1000 steps")
     else:
@@ -208,9 +253,12 @@ def bench_other(args):
     else:
         steps_per_map = work[-1]
     kern_s = sum(kernel_ms) / len(kernel_ms) / 1e3
-    achieved = fl * steps_per_map / kern_s / 1e12
-    rl.update({"achieved": round(achieved, 3), "frac": round(achieved / rl["peak"], 4), "traffic": None,
-               "kernel_ms": round(kern_s * 1e3, 3)})
+    if "engine" in rl:
+        rl = kernel_roofline(rl["engine"], K, fl, steps_per_map, kern_s, None)
+    else:
+        achieved = fl * steps_per_map / kern_s / 1e12
+        rl.update({"achieved": round(achieved, 3), "frac": round(achieved / rl["peak"], 4), "traffic": None,
+                   "kernel_ms": round(kern_s * 1e3, 3)})
     out = {"metric": "particle-steps/s at 1 GPU", "value": steps_per_map * args.steps / elapsed,
            "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
@@ -235,6 +283,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "kernel that calibrates the profiler's FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--engine", default="auto", choices=["auto", "valu", "mfma"],
+                    help="velocity engine of the FP32 torus time kernel (auto = matrix cores for K <= 7)")
     ap.add_argument("--workload", default="torus-k6-fp32",
                     help="torus-k6-fp32 (the benchmark line), torus-k80-turbulent, disk-dirichlet, torus-k6-batch")
     args = ap.parse_args()
@@ -255,10 +305,12 @@ def main():
     dev = torch.device("cuda", 0)
     ctx = pm.Context(0)
     ctx.set_tuning(args.ppl, args.coef_source)
+    ctx.set_time_engine(args.engine)
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
     u = torch.tensor(wl.u, dtype=torch.float64, device=dev)
     obs = torch.tensor(wl.obs, dtype=torch.float64, device=dev)
     K = int(abs(wl.modes).max())
+    engine = engine_in_use(pm, args.engine, K)
     steps_per_map = wl.n_obs * wl.n_particles * wl.n_steps
 
     if args.copy_mib > 0:
@@ -268,8 +320,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     tuned = None
-    if not args.no_autotune and args.ppl == 0:
-        # untimed setup: pick the fastest kernel variant (results are identical for all)
+    if engine == "valu" and not args.no_autotune and args.ppl == 0:
+        # untimed setup: pick the fastest vector-kernel variant (results are identical for all)
         tuned = prob.autotune_time(u, obs, wl.kappa, wl.dt, wl.n_particles, wl.seed, n_probe_steps=100)
         ctx.set_tuning(0, 0)
 
@@ -298,17 +350,10 @@ def main():
 
     fl = flops_per_particle_step(K)
     kern_s = sum(kernel_ms) / len(kernel_ms) / 1e3
-    achieved = fl * steps_per_map / kern_s / 1e12
-    traffic = None
-    if COUNTER_TRAFFIC_BYTES is not None and kernel_sources_sha256() == KERNEL_SOURCES_SHA256:
-        traffic = COUNTER_TRAFFIC_BYTES
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                "traffic_unit": "bytes per launch",
-                "kernel": "k_time<float,6>", "kernel_ms": round(kern_s * 1e3, 3),
-                "flop_per_particle_step": fl,
-                "variant": tuned if tuned else {"particles_per_lane": args.ppl or 2,
-                                                "coef_source": args.coef_source}}
+    roofline = kernel_roofline(engine, K, fl, steps_per_map, kern_s, counter_traffic(engine))
+    if engine == "valu":
+        roofline["variant"] = tuned if tuned else {"particles_per_lane": args.ppl or 2,
+                                                   "coef_source": args.coef_source}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -101,6 +101,15 @@ typedef struct {
  * three products, FP32 accumulation; about FP32 accuracy).  This is the
  * regime of Section 4's turbulent example, |k|_2 <= 80 (20,081 modes). */
 #define PM_MAX_K_MFMA 95
+/* FP32 torus problems with 1 <= K <= PM_MAX_K_MX (B = 2K + 1 <= 15 basis
+ * functions per axis) run the same bilinear forms on the matrix cores by
+ * default (engine PM_ENGINE_AUTO; see pm_set_time_engine). */
+#define PM_MAX_K_MX 7
+
+/* Velocity engines of the FP32 torus time path (pm_set_time_engine). */
+#define PM_ENGINE_AUTO 0 /* matrix cores where they apply (K <= PM_MAX_K_MX), else vector units */
+#define PM_ENGINE_VALU 1 /* vector units: FP32 fused multiply-adds */
+#define PM_ENGINE_MFMA 2 /* matrix cores where they apply (the same as AUTO) */
 
 /* Create a context on HIP device `device` that enqueues on `stream`
  * (a hipStream_t; NULL = the null stream).  Returns PM_OK, PM_EINVAL or
@@ -257,11 +266,27 @@ int pm_last_kernel_stats(pm_ctx *ctx, double *ms, double *particle_steps);
 
 const char *pm_strerror(int status);
 
-/* Kernel tuning knob for the time kernel: particles per lane (1 to 4) and
+/* Kernel tuning knob for the vector time kernel: particles per lane (1 to 4) and
  * coefficient source (0 = LDS, 1 = scalar cache).  particles_per_lane = 0
  * selects the autotuned choice for the problem's K, else 2 particles per lane.
  * Every choice gives bitwise identical results. */
 int pm_set_tuning(pm_ctx *ctx, int particles_per_lane, int coef_source);
+
+/* Velocity engine of the FP32 torus time problem (Algorithm 1, eq. euler
+ * with the field of eq. v_expand), used by pm_observe_time, _multi, _batch,
+ * pm_jacobian_time, the graphs and pm_step / pm_velocity:
+ *   PM_ENGINE_AUTO (default) or PM_ENGINE_MFMA: for 1 <= K <= PM_MAX_K_MX
+ *     the two bilinear forms of 64 particles are one matrix-core contraction
+ *     (v_mfma_f32_32x32x16_f16 on coefficients and x basis split into FP16
+ *     hi + lo halves, three products, FP32 accumulation: velocity errors
+ *     near 1e-6 of max |v|, paths within the FP32 error contract);
+ *   PM_ENGINE_VALU: FP32 fused multiply-adds on the vector units (the
+ *     kernel that pm_set_tuning and pm_autotune_time tune).
+ * The two engines round differently, so their results agree to that
+ * contract, not bit for bit; each is deterministic.  FP64 problems, other
+ * domains and K > PM_MAX_K_MX ignore the setting.  Returns PM_EINVAL for
+ * another value or a closed context. */
+int pm_set_time_engine(pm_ctx *ctx, int engine);
 
 /* Coefficient source of the Dirichlet walk: 0 = LDS, 1 = scalar cache
  * (default).  Both give bitwise identical results. */

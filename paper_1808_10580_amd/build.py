@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpm.so")
-SOURCES = ["pm_kernels.hip", "pm_abi.hip", "pm_mlp.hip", "pm_hk.hip", "pm_graph.hip"]
+SOURCES = ["pm_kernels.hip", "pm_abi.hip", "pm_mlp.hip", "pm_hk.hip", "pm_mx.hip", "pm_graph.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -25,9 +25,14 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-t
           "-Wno-unused-but-set-variable", "-munsafe-fp-atomics"]
 
 
+# The small-K matrix-core kernel keeps its MFMA accumulators in ordinary
+# VGPRs (no AGPR copies between the contraction and the y form).
+EXTRA = {"pm_mx.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *COMMON, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -52,7 +57,7 @@ def build(asm: bool = False, jobs: int = 4) -> str:
     if asm:
         for s in srcs:
             out = os.path.join(BUILD, s.replace(".hip", ".s"))
-            cmd = [HIPCC, *COMMON, "--cuda-device-only", "-S", os.path.join(CSRC, s), "-o", out]
+            cmd = [HIPCC, *COMMON, *EXTRA.get(s, []), "--cuda-device-only", "-S", os.path.join(CSRC, s), "-o", out]
             subprocess.run(cmd, check=True)
     return LIB
 

@@ -11,7 +11,7 @@
 #include <new>
 #include <vector>
 
-#include "pm_kernels.h"
+#include "pm_mx.h"
 
 using namespace pm;
 
@@ -71,6 +71,9 @@ struct pm_ctx {
     int dir_launches = 8;          // ... over this many follow-up launches
     void *pool = nullptr;          // compaction pools: counters, states, indices
     size_t pool_cap = 0;
+    int engine = PM_ENGINE_AUTO;   // velocity engine of the FP32 torus time path
+    void *mx = nullptr;            // small-K matrix-core operands [n_sets][MX_SET_BYTES]
+    size_t mx_cap = 0;
     int tune_ppl[PM_MAX_K + 1] = {0};  // autotuned choice per harmonic count K
     int tune_src[PM_MAX_K + 1] = {0};
     bool capturing = false;  // recording a graph: no timing events, no host waits
@@ -218,6 +221,34 @@ int fold_hk(pm_ctx *c, const pm_problem *p, const double *u, int n_sets, int64_t
     if (launch_fold_hk(fa, (unsigned char *)c->coef, n_sets, c->stream) != hipSuccess) return PM_EDEVICE;
     *out = (const unsigned char *)c->coef;
     *set_bytes = sb;
+    return PM_OK;
+}
+
+// The small-K matrix-core velocity serves FP32 torus problems with
+// 1 <= K <= MX_MAX_K unless the vector engine is requested.
+bool use_mx(const pm_ctx *c, const pm_problem *p)
+{
+    return c->engine != PM_ENGINE_VALU && p->domain == PM_TORUS && p->prec == PM_FP32 && !p->hk && p->K >= 1 &&
+           p->K <= MX_MAX_K;
+}
+
+// FP64 fold, then the split-FP16 operands of the small-K matrix-core path.
+int fold_mx(pm_ctx *c, const pm_problem *p, const double *u, int n_sets, int64_t u_stride,
+            const unsigned char **out)
+{
+    double *coef;
+    int64_t cs;
+    int st = fold<double>(c, p, u, n_sets, u_stride, &coef, &cs);
+    if (st) return st;
+    st = ensure(c, &c->mx, &c->mx_cap, (size_t)n_sets * MX_SET_BYTES);
+    if (st) return st;
+    MxPackArgs pa{};
+    pa.coef = coef;
+    pa.coef_stride = cs;
+    pa.K = p->K;
+    pa.row_stride = row_stride(p->domain, p->K);
+    if (launch_pack_mx(pa, (unsigned char *)c->mx, n_sets, c->stream) != hipSuccess) return PM_EDEVICE;
+    *out = (const unsigned char *)c->mx;
     return PM_OK;
 }
 
@@ -369,13 +400,17 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
             return observe_time_hk(c, p, n_u, u, nps, seeds, obs, n_obs, kappa, dte, reads, n_read, mean, var,
                                    endpoints);
     }
-    T *coef;
-    int64_t cstride;
-    int st = fold<T>(c, p, u, n_u, 2 * (int64_t)p->n_modes, &coef, &cstride);
+    bool mx = false;
+    if constexpr (std::is_same<T, float>::value) mx = use_mx(c, p);
+    T *coef = nullptr;
+    int64_t cstride = 0;
+    const unsigned char *mx_sets = nullptr;
+    int st = mx ? fold_mx(c, p, u, n_u, 2 * (int64_t)p->n_modes, &mx_sets)
+                : fold<T>(c, p, u, n_u, 2 * (int64_t)p->n_modes, &coef, &cstride);
     if (st) return st;
 
-    int ppl = 1, src = PM_COEF_LDS;
-    if (!std::is_same<T, double>::value) {
+    int ppl = 1, src = PM_COEF_LDS;  // the matrix-core kernel: one chunk per task
+    if (!std::is_same<T, double>::value && !mx) {
         if (n_read > 1) {
             ppl = 2;  // the multi-readout kernel's one FP32 variant
             src = PM_COEF_SCALAR;
@@ -481,7 +516,20 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
 
     if (launch_zero_u64(c->d_queue, 1, c->stream) != hipSuccess) return PM_EDEVICE;
     if (!c->capturing) PM_HIP(hipEventRecord(c->ev0, c->stream));
-    if (launch_time<T>(a, p->K, ppl, src, c->n_cu, c->bpc, c->stream) != hipSuccess) return PM_EDEVICE;
+    hipError_t le;
+    if constexpr (std::is_same<T, float>::value) {
+        if (mx) {
+            MxTimeArgs ma{};
+            ma.t = a;
+            ma.sets = mx_sets;
+            le = launch_time_mx(ma, p->K, c->n_cu, c->bpc, c->stream);
+        } else {
+            le = launch_time<T>(a, p->K, ppl, src, c->n_cu, c->bpc, c->stream);
+        }
+    } else {
+        le = launch_time<T>(a, p->K, ppl, src, c->n_cu, c->bpc, c->stream);
+    }
+    if (le != hipSuccess) return PM_EDEVICE;
     if (!c->capturing) {
         PM_HIP(hipEventRecord(c->ev1, c->stream));
         c->timed = true;
@@ -728,7 +776,7 @@ void pm_destroy(pm_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     void *bufs[] = {c->d_flags, c->d_queue, c->coef, c->part, c->part2, c->pay, c->tau, c->capped,
                     c->meta, c->states, c->exitp, c->integ, c->nsteps, c->order, c->fd_u, c->fd_m,
-                    c->integ_src, c->part3, c->src_var, c->pool};
+                    c->integ_src, c->part3, c->src_var, c->pool, c->mx};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->h_meta) (void)hipHostFree(c->h_meta);
@@ -753,6 +801,14 @@ int pm_set_tuning(pm_ctx *c, int ppl, int src)
     if (!(src == 0 || src == 1)) return PM_EINVAL;
     c->ppl = ppl;
     c->src = src;
+    return PM_OK;
+}
+
+int pm_set_time_engine(pm_ctx *c, int engine)
+{
+    if (!c || c->closed) return PM_EINVAL;
+    if (engine != PM_ENGINE_AUTO && engine != PM_ENGINE_VALU && engine != PM_ENGINE_MFMA) return PM_EINVAL;
+    c->engine = engine;
     return PM_OK;
 }
 
@@ -1031,6 +1087,29 @@ static int step_hk(pm_ctx *c, const pm_problem *p, const double *u, int64_t coun
     return launch_step_hk(a, c->stream) == hipSuccess ? PM_OK : PM_EDEVICE;
 }
 
+static int step_mx(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, const double *X,
+                   const uint64_t *n, const uint32_t *i, const uint32_t *j, double kappa, double dt,
+                   uint64_t seed, double *Y, double *V)
+{
+    const unsigned char *set;
+    int st = fold_mx(c, p, u, 1, 2 * (int64_t)p->n_modes, &set);
+    if (st) return st;
+    MxStepArgs a{};
+    a.set = set;
+    a.count = count;
+    a.X = X;
+    a.n = n;
+    a.i = i;
+    a.j = j;
+    a.seed = seed;
+    a.sc = step_consts<float>(dt, kappa);
+    a.v0x = (float)p->v0[0];
+    a.v0y = (float)p->v0[1];
+    a.Y = Y;
+    a.V = V;
+    return launch_step_mx(a, p->K, c->stream) == hipSuccess ? PM_OK : PM_EDEVICE;
+}
+
 int pm_step(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, const double *X,
             const uint64_t *n, const uint32_t *i, const uint32_t *j, double kappa, double dt,
             uint64_t seed, double *Y)
@@ -1043,6 +1122,7 @@ int pm_step(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, cons
     if (!(std::isfinite(kappa) && kappa >= 0.0) || !finite_pos(dt)) return PM_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
     if (p->hk) return step_hk(c, p, u, count, X, n, i, j, kappa, dt, seed, Y, nullptr);
+    if (use_mx(c, p)) return step_mx(c, p, u, count, X, n, i, j, kappa, dt, seed, Y, nullptr);
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);
         T *coef;
@@ -1075,6 +1155,7 @@ int pm_velocity(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, 
     if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(X) || bad_ptr(V)) return PM_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
     if (p->hk) return step_hk(c, p, u, count, X, nullptr, nullptr, nullptr, 0.0, 1.0, 0, nullptr, V);
+    if (use_mx(c, p)) return step_mx(c, p, u, count, X, nullptr, nullptr, nullptr, 0.0, 1.0, 0, nullptr, V);
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);
         T *coef;
@@ -1192,6 +1273,7 @@ int pm_graph_create_time(pm_ctx *c, const pm_problem *p, int n_u, const double *
     q->ppl = c->ppl;
     q->src = c->src;
     q->bpc = c->bpc;
+    q->engine = c->engine;
     for (int k = 0; k <= PM_MAX_K; ++k) {
         q->tune_ppl[k] = c->tune_ppl[k];
         q->tune_src[k] = c->tune_src[k];
@@ -1278,7 +1360,8 @@ int pm_autotune_time(pm_ctx *c, const pm_problem *p, const double *u, const doub
     }
     double *tmp = nullptr;
     if (hipMalloc((void **)&tmp, 2 * (size_t)n_obs * sizeof(double)) != hipSuccess) return PM_ENOMEM;
-    const int save_ppl = c->ppl, save_src = c->src;
+    const int save_ppl = c->ppl, save_src = c->src, save_engine = c->engine;
+    c->engine = PM_ENGINE_VALU;  // the probes time the vector kernel's variants
     const double T = n_probe_steps * dt;
     int best_ppl = 2, best_src = PM_COEF_LDS;
     double best = 1e300;
@@ -1313,6 +1396,7 @@ int pm_autotune_time(pm_ctx *c, const pm_problem *p, const double *u, const doub
     }
     c->ppl = save_ppl;
     c->src = save_src;
+    c->engine = save_engine;
     (void)hipFree(tmp);
     if (st) return st;
     c->tune_ppl[p->K] = best_ppl;

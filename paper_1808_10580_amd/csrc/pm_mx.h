@@ -1,0 +1,54 @@
+// pm_mx.h -- argument blocks and launchers of the small-K matrix-core
+// velocity engine (pm_mx.hip), shared with the C ABI (pm_abi.hip).
+#pragma once
+
+#include "pm_kernels.h"
+
+namespace pm {
+
+// ---------------------------------------------------------------------------
+// Small-K torus path (pm_mx.hip): split-FP16 matrix-core velocity for
+// 1 <= K <= MX_MAX_K (B = 2K + 1 <= 16 basis functions per axis).
+// ---------------------------------------------------------------------------
+constexpr int MX_MAX_K = 7;
+constexpr int MX_BASIS_SHIFT = 8;        // the x basis enters the products scaled by 2^8
+constexpr int64_t MX_SET_BYTES = 2112;   // per parameter set: 64-byte header, A hi, A lo (64 lanes x 16 B)
+
+struct MxHeader {
+    float inv_scale;  // 2^-(coefficient shift + MX_BASIS_SHIFT)
+    float cmax;       // max |Cx|, |Cy|
+    float pad[14];
+};
+static_assert(sizeof(MxHeader) == 64, "operand alignment");
+
+struct MxPackArgs {
+    const double *coef;   // FP64 torus coefficients of k_fold, [n_sets][coef_stride]
+    int64_t coef_stride;
+    int K;
+    int row_stride;
+};
+
+struct MxTimeArgs {
+    TimeArgs<float> t;           // chunk layout, steps, readouts, outputs (t.coef unused)
+    const unsigned char *sets;   // [n_u][MX_SET_BYTES]
+};
+
+struct MxStepArgs {
+    const unsigned char *set;  // one parameter set
+    int64_t count;
+    const double *X;
+    const uint64_t *n;
+    const uint32_t *i;
+    const uint32_t *j;
+    uint64_t seed;
+    StepConsts<float> sc;
+    float v0x, v0y;
+    double *Y;  // step mode
+    double *V;  // velocity mode when non-null (n, i, j, Y unused)
+};
+
+hipError_t launch_pack_mx(const MxPackArgs &a, unsigned char *out, int n_sets, hipStream_t st);
+hipError_t launch_time_mx(const MxTimeArgs &a, int K, int n_cu, int bpc, hipStream_t st);
+hipError_t launch_step_mx(const MxStepArgs &a, int K, hipStream_t st);
+
+}  // namespace pm

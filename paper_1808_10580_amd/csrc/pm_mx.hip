@@ -1,0 +1,429 @@
+// pm_mx.hip -- the velocity field of eq. v_expand on the torus for small
+// wavenumber cutoffs (1 <= K <= 7, B = 2K + 1 <= 15 basis functions per
+// axis), FP32 particles, with the bilinear forms on the matrix cores.
+//
+// With the axis bases phi_0 = 1, phi_{2n-1} = cos 2 pi n s, phi_{2n} =
+// sin 2 pi n s the field is
+//     v_x(x, y) = phi(x)^T Cx phi(y),   v_y(x, y) = phi(x)^T Cy phi(y),
+// 2 B^2 multiply-adds per particle (338 at K = 6), about three quarters of
+// all the arithmetic of an Euler-Maruyama step.  For the 64 particles of a
+// wave the inner products W = [Cx; Cy]^T Phi_x are one dense contraction
+// (32 rows: 16 per component, B <= 16 x-basis functions, 64 particles) on
+// v_mfma_f32_32x32x16_f16.  Operands are split into FP16 pairs (a = a_hi +
+// a_lo) and three products a_hi b_hi + a_hi b_lo + a_lo b_hi are accumulated
+// in FP32: about 2^-22 relative error per product.  The x basis enters
+// scaled by 2^8 and the coefficients by a power of two that puts max |C| in
+// [2^14, 2^15), so the low halves stay normal FP16 numbers; the result is
+// scaled back exactly.
+//
+// Matrix-core layouts (32x32x16, lane l, h = l / 32):
+//   A (32 rows x 16 cols i): lane l holds row l % 32, cols i = 8 h + e (e = 0..7);
+//                            row q < 16 is Cx[i][j = q], row q >= 16 is Cy[i][j = q - 16]
+//   B (16 rows i x 32 cols): lane l holds phi_{8 h + e}(x_p), p = 32 b + l % 32 (column block b)
+//   D (32 x 32, FP32):       lane l holds W[q = 8 (r / 4) + 4 h + r % 4][p = 32 b + l % 32], r = 0..15
+// Lane l holds particle l.  Every lane computes its own particle's bases; one
+// v_permlane32_swap per register pair (it swaps the upper half-wave of one
+// register with the lower half-wave of another) moves the halves that the
+// other half-wave's lanes need: lanes l and l ^ 32 exchange x-basis entries
+// 8..15 / 0..7, and y-basis entries {4..7, 12..15} / {0..3, 8..11}, the rows
+// that their D registers hold.  A last swap pairs the two half sums of each
+// particle in a fixed order, so the result is identical in every launch
+// shape.
+#include "pm_mx.h"
+
+namespace pm {
+
+typedef _Float16 h16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Operand packing: FP64 coefficients (torus rows of k_fold: row j holds
+// Cx[i][j], Cy[i][j] at [2i], [2i+1]) -> scaled FP16 pairs in the A layout.
+// One block per parameter set; a fixed max-reduction tree.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pack_mx(const MxPackArgs a, unsigned char *__restrict__ out)
+{
+    __shared__ double red[256];
+    const int B = 2 * a.K + 1;
+    const int R = a.row_stride;
+    const double *__restrict__ C = a.coef + (int64_t)blockIdx.x * a.coef_stride;
+    double m = 0.0;
+    for (int e = threadIdx.x; e < 2 * B * B; e += blockDim.x) {
+        const int j = e / (2 * B), q = e % (2 * B);
+        m = fmax(m, fabs(C[j * R + q]));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const double cmax = red[0];
+    int sc = 0;
+    if (cmax > 0.0) {
+        int ex;
+        frexp(cmax, &ex);  // cmax = f 2^ex, f in [0.5, 1)
+        sc = 15 - ex;
+        // tiny fields keep a representable scale (their velocity is ~0 anyway)
+        sc = sc > 100 ? 100 : (sc < -100 ? -100 : sc);
+    }
+    unsigned char *set = out + (int64_t)blockIdx.x * MX_SET_BYTES;
+    MxHeader *hd = reinterpret_cast<MxHeader *>(set);
+    if (threadIdx.x == 0) {
+        hd->inv_scale = ldexpf(1.f, -(sc + MX_BASIS_SHIFT));
+        hd->cmax = (float)cmax;
+        for (int q = 0; q < 14; ++q) hd->pad[q] = 0.f;
+    }
+    _Float16 *hi = reinterpret_cast<_Float16 *>(set + sizeof(MxHeader));
+    _Float16 *lo = hi + 64 * 8;
+    for (int t = threadIdx.x; t < 64 * 8; t += blockDim.x) {
+        const int lane = t >> 3, e = t & 7;
+        const int row = lane & 31, i = 8 * (lane >> 5) + e;
+        const int comp = row >> 4, j = row & 15;
+        double v = 0.0;
+        if (i < B && j < B) v = ldexp(C[j * R + 2 * i + comp], sc);
+        const _Float16 h = (_Float16)(float)v;
+        hi[t] = h;
+        lo[t] = (_Float16)(float)(v - (double)(float)h);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Velocity of the 64 particles of a wave at (xh, yh); every lane of the wave
+// must call it (lanes without a particle pass any finite position).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void swap_halves(uint32_t &p, uint32_t &q)
+{
+    const auto s = __builtin_amdgcn_permlane32_swap(p, q, false, false);
+    p = s[0];
+    q = s[1];
+}
+
+__device__ __forceinline__ void swap_halves(float &p, float &q)
+{
+    uint32_t a = __builtin_bit_cast(uint32_t, p), b = __builtin_bit_cast(uint32_t, q);
+    swap_halves(a, b);
+    p = __builtin_bit_cast(float, a);
+    q = __builtin_bit_cast(float, b);
+}
+
+// The x basis scaled by 2^MX_BASIS_SHIFT: the recurrence of trig_basis run on
+// scaled values with the unscaled rotation (c1, s1).  Scaling by a power of
+// two commutes with every rounding, so entry e equals 2^8 phi_e exactly.
+template <int K>
+__device__ __forceinline__ void scaled_basis(float s, float *phi)
+{
+    constexpr float S = (float)(1 << MX_BASIS_SHIFT);
+    float s1, c1;
+    sincos_rev(s, s1, c1);
+    phi[0] = S;
+    phi[1] = c1 * S;
+    phi[2] = s1 * S;
+    float c = phi[1], sn = phi[2];
+#pragma unroll
+    for (int n = 2; n <= K; ++n) {
+        const float cn = __builtin_fmaf(c, c1, -(sn * s1));
+        const float snn = __builtin_fmaf(sn, c1, c * s1);
+        c = cn;
+        sn = snn;
+        phi[2 * n - 1] = c;
+        phi[2 * n] = sn;
+    }
+}
+
+// FP16 pairs of two values: hi = (f16(v0), f16(v1)) and lo = (f16(v0 - hi0),
+// f16(v1 - hi1)), each half written in place by a mixed-precision FMA (v * 1
+// - hi is exact in the FMA, so lo is the correctly rounded remainder).
+__device__ __forceinline__ void split_pair(float v0, float v1, uint32_t &hi, uint32_t &lo)
+{
+    uint32_t h, l;
+    asm("v_fma_mixlo_f16 %0, %1, 1.0, 0" : "=v"(h) : "v"(v0));
+    asm("v_fma_mixhi_f16 %0, %1, 1.0, 0" : "+v"(h) : "v"(v1));
+    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(l) : "v"(v0), "v"(h));
+    asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "+v"(l) : "v"(v1), "v"(h));
+    hi = h;
+    lo = l;
+}
+
+template <int K>
+__device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, float inv, float xh, float yh,
+                                            float &vx, float &vy)
+{
+    constexpr int B = 2 * K + 1;
+    static_assert(K >= 1 && B <= 16, "small-K path");
+    // x basis x 2^8 split into FP16 pairs; P holds entries 0..7, Q 8..15
+    // (entries past B are zero)
+    float px[16];
+    scaled_basis<K>(xh, px);
+    uint32_t Ph[4], Pl[4], Qh[4], Ql[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int e = 8 * half + 2 * d;
+            uint32_t hi = 0u, lo = 0u;
+            if (e < B) split_pair(px[e], e + 1 < B ? px[e + 1] : 0.f, hi, lo);
+            (half ? Qh : Ph)[d] = hi;
+            (half ? Ql : Pl)[d] = lo;
+        }
+    }
+    // after the swaps P is the B operand of column block 0 (particles 0..31)
+    // and Q that of column block 1 (particles 32..63)
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        swap_halves(Ph[d], Qh[d]);
+        swap_halves(Pl[d], Ql[d]);
+    }
+    const h16x8 b0h = __builtin_bit_cast(h16x8, (u32x4){Ph[0], Ph[1], Ph[2], Ph[3]});
+    const h16x8 b0l = __builtin_bit_cast(h16x8, (u32x4){Pl[0], Pl[1], Pl[2], Pl[3]});
+    const h16x8 b1h = __builtin_bit_cast(h16x8, (u32x4){Qh[0], Qh[1], Qh[2], Qh[3]});
+    const h16x8 b1l = __builtin_bit_cast(h16x8, (u32x4){Ql[0], Ql[1], Ql[2], Ql[3]});
+    f32x16 d0 = {}, d1 = {};
+    d0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, b0h, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, b1h, d1, 0, 0, 0);
+    d0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, b0l, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, b1l, d1, 0, 0, 0);
+    d0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, b0h, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, b1h, d1, 0, 0, 0);
+
+    // y basis (FP32, unscaled) while the matrix cores work: Py = entries
+    // {0..3, 8..11}, Qy = {4..7, 12..15}; after the swaps Py serves column
+    // block 0 and Qy block 1, entry q matching D register q (x rows) and
+    // 8 + q (y rows)
+    float py[16];
+    trig_basis<float, K>(yh, py);
+#pragma unroll
+    for (int e = B; e < 16; ++e) py[e] = 0.f;
+    float Py[8], Qy[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int jl = (q < 4) ? q : q + 4;  // 0..3, 8..11
+        Py[q] = py[jl];
+        Qy[q] = py[jl + 4];
+        swap_halves(Py[q], Qy[q]);
+    }
+    float ax0 = 0.f, ay0 = 0.f, ax1 = 0.f, ay1 = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        ax0 = __builtin_fmaf(d0[q], Py[q], ax0);
+        ay0 = __builtin_fmaf(d0[8 + q], Py[q], ay0);
+        ax1 = __builtin_fmaf(d1[q], Qy[q], ax1);
+        ay1 = __builtin_fmaf(d1[8 + q], Qy[q], ay1);
+    }
+    // lane l < 32 owns particle l of block 0 (its rows and those of lane
+    // l + 32); lane l >= 32 owns particle l of block 1.  After the swap every
+    // lane adds (lower half-wave rows) + (upper half-wave rows).
+    swap_halves(ax0, ax1);
+    swap_halves(ay0, ay1);
+    vx = (ax0 + ax1) * inv;
+    vy = (ay0 + ay1) * inv;
+}
+
+__device__ __forceinline__ void load_set(const unsigned char *__restrict__ set, int lane, h16x8 &ahi, h16x8 &alo,
+                                         float &inv)
+{
+    const h16x8 *t = reinterpret_cast<const h16x8 *>(set + sizeof(MxHeader));
+    ahi = t[lane];
+    alo = t[64 + lane];
+    inv = reinterpret_cast<const MxHeader *>(set)->inv_scale;
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1, persistent: one task is one 64-particle chunk of one parameter
+// set, one wave per task; lane l of chunk q of observation j runs particle
+// i = 64 q + l (the chunk layout and the Philox streams of the vector time
+// kernel, so the payoff and reduction kernels are shared).
+// ---------------------------------------------------------------------------
+template <int K, bool MT>
+__global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
+{
+    const TimeArgs<float> &a = m.t;
+    const int lane = threadIdx.x & 63;
+    int cur_b = -1;
+    h16x8 ahi = {}, alo = {};
+    float inv = 0.f;
+    for (;;) {
+        unsigned long long tk = 0;
+        if (lane == 0) tk = atomicAdd(a.queue, 1ull);
+        const unsigned long long t0 = __shfl(tk, 0);
+        const uint32_t tlo = __builtin_amdgcn_readfirstlane((uint32_t)t0);
+        const uint32_t thi = __builtin_amdgcn_readfirstlane((uint32_t)(t0 >> 32));
+        const int64_t task = (int64_t)(((uint64_t)thi << 32) | tlo);
+        if (task >= a.n_tasks) break;
+
+        int b = 0;
+        int64_t tb = 0, cb = 0, np = a.np0;
+        uint64_t seed = a.seed0;
+        if (a.n_u > 1) {
+            int lo = 0, hi = a.n_u - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.task_off[mid] <= task) lo = mid;
+                else hi = mid - 1;
+            }
+            b = __builtin_amdgcn_readfirstlane(lo);
+            tb = a.task_off[b];
+            cb = a.chunk_off[b];
+            np = a.np_arr[b];
+            seed = a.seed_arr[b];
+        }
+        if (b != cur_b) {
+            load_set(m.sets + (int64_t)b * MX_SET_BYTES, lane, ahi, alo, inv);
+            cur_b = b;
+        }
+        const int64_t cpo = (np + 63) >> 6;
+        const int64_t ch = task - tb;  // chunk within the set (< cpo * n_obs)
+        const int64_t j = ch / cpo;
+        const int64_t i = (ch - j * cpo) * 64 + lane;
+        const uint32_t pi = (uint32_t)i, pj = (uint32_t)j;
+        const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+
+        Coord<float> x, y;
+        x.set(a.obs[2 * j]);
+        y.set(a.obs[2 * j + 1]);
+
+        auto step = [&](float z0, float z1) {
+            float vx, vy;
+            mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy);
+            x.advance(vx + a.v0x, z0, a.sc);
+            y.advance(vy + a.v0y, z1, a.sc);
+            x.wrap();
+            y.wrap();
+        };
+        int r = 0;
+        int64_t next = a.read_at[0];
+        auto readout = [&](int64_t done) {
+            if (MT && done == next) {
+                double *S = a.states + r * a.read_stride + 2 * ((cb + ch) * 64 + lane);
+                S[0] = x.value();
+                S[1] = y.value();
+                ++r;
+                next = r < a.n_read ? a.read_at[r] : -1;
+            }
+        };
+        readout(0);
+        int64_t n = 0;
+        for (; n + 1 < a.n_steps; n += 2) {
+            const U4 w = philox4x32_10((uint32_t)(n >> 1), pi, pj, 0u, k0, k1);
+            float z0, z1, z2, z3;
+            box_muller(w.x, w.y, z0, z1);
+            box_muller(w.z, w.w, z2, z3);
+            step(z0, z1);
+            readout(n + 1);
+            step(z2, z3);
+            readout(n + 2);
+        }
+        if (n < a.n_steps) {
+            const U4 w = philox4x32_10((uint32_t)(n >> 1), pi, pj, 0u, k0, k1);
+            float z0, z1;
+            box_muller(w.x, w.y, z0, z1);
+            step(z0, z1);
+            readout(n + 1);
+        }
+        if (!MT) {
+            double *S = a.states + 2 * ((cb + ch) * 64 + lane);
+            S[0] = x.value();
+            S[1] = y.value();
+        }
+    }
+}
+
+// Teacher-forced steps and velocity at given points.  Each wave takes 64
+// consecutive entries; lanes past count use the origin.
+template <int K>
+__global__ __launch_bounds__(256) void k_step_mx(const MxStepArgs a)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool act = e < a.count;
+    h16x8 ahi, alo;
+    float inv;
+    load_set(a.set, lane, ahi, alo, inv);
+    Coord<float> x, y;
+    x.set(act ? a.X[2 * e] : 0.0);
+    y.set(act ? a.X[2 * e + 1] : 0.0);
+    float vx, vy;
+    mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy);
+    if (!act) return;
+    if (a.V) {
+        a.V[2 * e] = (double)(vx + a.v0x);
+        a.V[2 * e + 1] = (double)(vy + a.v0y);
+        return;
+    }
+    const uint64_t n = a.n[e];
+    const U4 w = philox4x32_10((uint32_t)(n >> 1), a.i[e], a.j[e], 0u, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+    float z0, z1;
+    if ((n & 1) == 0) box_muller(w.x, w.y, z0, z1);
+    else box_muller(w.z, w.w, z0, z1);
+    x.advance(vx + a.v0x, z0, a.sc);
+    y.advance(vy + a.v0y, z1, a.sc);
+    double nx = x.value(), ny = y.value();
+    nx -= floor(nx);
+    ny -= floor(ny);
+    a.Y[2 * e] = nx;
+    a.Y[2 * e + 1] = ny;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+template <typename F>
+static hipError_t dispatch_mx(int K, F &&f)
+{
+    switch (K) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    case 7: return f(std::integral_constant<int, 7>{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pack_mx(const MxPackArgs &a, unsigned char *out, int n_sets, hipStream_t st)
+{
+    if (a.K < 1 || a.K > MX_MAX_K || n_sets < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pack_mx, dim3(n_sets), dim3(256), 0, st, a, out);
+    return hipGetLastError();
+}
+
+template <int K, bool MT>
+static hipError_t launch_time_mx_k(const MxTimeArgs &a, int n_cu, int bpc, hipStream_t st)
+{
+    auto kern = k_time_mx<K, MT>;
+    int per_cu = 0;
+    hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
+    if (err != hipSuccess) return err;
+    if (per_cu < 1) per_cu = 1;
+    if (bpc > 0 && bpc < per_cu) per_cu = bpc;
+    int64_t blocks = (int64_t)per_cu * n_cu;
+    const int64_t need = (a.t.n_tasks + 3) / 4;  // one task per wave
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_time_mx(const MxTimeArgs &a, int K, int n_cu, int bpc, hipStream_t st)
+{
+    return dispatch_mx(K, [&](auto kc) -> hipError_t {
+        constexpr int KK = decltype(kc)::value;
+        if (a.t.n_read > 1) return launch_time_mx_k<KK, true>(a, n_cu, bpc, st);
+        return launch_time_mx_k<KK, false>(a, n_cu, bpc, st);
+    });
+}
+
+hipError_t launch_step_mx(const MxStepArgs &a, int K, hipStream_t st)
+{
+    return dispatch_mx(K, [&](auto kc) -> hipError_t {
+        constexpr int KK = decltype(kc)::value;
+        const int64_t blocks = (a.count + 255) / 256;
+        hipLaunchKernelGGL(k_step_mx<KK>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+        return hipGetLastError();
+    });
+}
+
+}  // namespace pm

@@ -6,6 +6,8 @@
   - the same for a captured batch of parameter sets;
   - the autotuner picks a valid variant and never changes results;
   - the batch of per-u particle counts and seeds equals separate calls.
+Graph checks run for both FP32 velocity engines (vector FMAs and the
+matrix-core contraction).
 """
 import numpy as np
 import pytest
@@ -36,8 +38,19 @@ def np_(t):
     return t.detach().cpu().numpy()
 
 
-def test_graph_replays_match_eager_bitwise(pm, ctx):
+@pytest.fixture
+def engine_of(ctx):
+    def use(name):
+        ctx.set_time_engine(name)
+        return name
+    yield use
+    ctx.set_time_engine("auto")
+
+
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+def test_graph_replays_match_eager_bitwise(pm, ctx, engine_of, engine):
     import torch
+    engine_of(engine)
     wl = W.time_main()
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
     rng = np.random.default_rng(5)
@@ -59,8 +72,10 @@ def test_graph_replays_match_eager_bitwise(pm, ctx):
     g.close()
 
 
-def test_batch_graph_matches_eager(pm, ctx):
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+def test_batch_graph_matches_eager(pm, ctx, engine_of, engine):
     import torch
+    engine_of(engine)
     wl = W.batch_main(n_u=6, lo=100, hi=3000)
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
     U = torch.tensor(wl.u, dtype=torch.float64, device="cuda").contiguous()
@@ -77,7 +92,8 @@ def test_batch_graph_matches_eager(pm, ctx):
         assert np.array_equal(mg, np_(me)) and np.array_equal(vg, np_(ve))
 
 
-def test_autotune_picks_a_variant_and_keeps_results(pm, ctx):
+def test_autotune_picks_a_variant_and_keeps_results(pm, ctx, engine_of):
+    engine_of("valu")  # the autotuner tunes the vector kernel
     wl = W.time_main()
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
     ctx.set_tuning(2, 0)

@@ -14,6 +14,8 @@ agreement is checked where it is physically meaningful):
       paired per-path differences, |mean d| <= 4 SE(d) per observation;
   plus bitwise determinism across launch shapes, batching = separate calls,
   ragged chunks, one particle, odd step counts and argument validation.
+FP32 checks run for both velocity engines: the vector FMAs ("valu") and the
+split-FP16 matrix-core contraction ("mfma", K <= 7), under the same bounds.
 Payoffs of both sides' endpoints for P4 are evaluated in the test with numpy,
 never by feeding GPU data into the oracle.
 """
@@ -54,6 +56,16 @@ def np_(t):
     return t.detach().cpu().numpy()
 
 
+@pytest.fixture
+def engine_of(ctx):
+    """Select a velocity engine for one test; the default is restored after."""
+    def use(name):
+        ctx.set_time_engine(name)
+        return name
+    yield use
+    ctx.set_time_engine("auto")
+
+
 def theta0_numpy(fd, X):
     """Test-side evaluation of the initial conditions used here."""
     x, y = X[..., 0], X[..., 1]
@@ -75,9 +87,10 @@ def theta0_numpy(fd, X):
 # P0: building blocks
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("K", [1, 2, 6, 8])
-def test_velocity_matches_oracle(pm, ctx, orc, prec, K):
+@pytest.mark.parametrize("prec,engine", [("fp64", "auto"), ("fp32", "valu"), ("fp32", "mfma")])
+@pytest.mark.parametrize("K", [1, 2, 6, 7, 8])
+def test_velocity_matches_oracle(pm, ctx, orc, engine_of, prec, engine, K):
+    engine_of(engine)
     rng = np.random.default_rng(K)
     modes = W.torus_modes(K)
     u = W.draw_prior(modes, rng)
@@ -87,7 +100,7 @@ def test_velocity_matches_oracle(pm, ctx, orc, prec, K):
     ref = orc.velocity("torus", modes, u, X, v0=(0.25, -0.5))
     scale = np.max(np.abs(ref))
     tol = 1e-12 if prec == "fp64" else 2e-5
-    print("velocity K=%d %s: max rel err %.2e" % (K, prec, np.max(np.abs(V - ref)) / scale))
+    print("velocity K=%d %s %s: max rel err %.2e" % (K, prec, engine, np.max(np.abs(V - ref)) / scale))
     assert np.max(np.abs(V - ref)) <= tol * scale
 
 
@@ -122,11 +135,14 @@ def test_normals_match_oracle(pm, ctx, orc, prec):
 # P1: teacher-forced steps
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("wl_name,prec,tol", [("torus-k2-fp64", "fp64", 1e-13),
-                                              ("torus-k2-fp64", "fp32", 1e-6),
-                                              ("torus-k6-fp32", "fp32", 1e-6),
-                                              ("torus-k6-fp32", "fp64", 1e-13)])
-def test_teacher_forced_steps(pm, ctx, orc, wl_name, prec, tol):
+@pytest.mark.parametrize("wl_name,prec,tol,engine", [("torus-k2-fp64", "fp64", 1e-13, "auto"),
+                                                     ("torus-k2-fp64", "fp32", 1e-6, "valu"),
+                                                     ("torus-k2-fp64", "fp32", 1e-6, "mfma"),
+                                                     ("torus-k6-fp32", "fp32", 1e-6, "valu"),
+                                                     ("torus-k6-fp32", "fp32", 1e-6, "mfma"),
+                                                     ("torus-k6-fp32", "fp64", 1e-13, "auto")])
+def test_teacher_forced_steps(pm, ctx, orc, engine_of, wl_name, prec, tol, engine):
+    engine_of(engine)
     wl = W.WORKLOADS[wl_name]()
     dte = wl.T / wl.n_steps
     rows = []
@@ -143,7 +159,7 @@ def test_teacher_forced_steps(pm, ctx, orc, wl_name, prec, tol):
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec=prec)
     Y = np_(prob.step(wl.u, X, n, i, j, wl.kappa, dte, wl.seed))
     d = tdist(Y, Yref)
-    print("teacher-forced %s %s: max %.2e median %.2e" % (wl_name, prec, d.max(), np.median(d)))
+    print("teacher-forced %s %s %s: max %.2e median %.2e" % (wl_name, prec, engine, d.max(), np.median(d)))
     assert np.max(d) <= tol
 
 
@@ -190,7 +206,9 @@ def check_fp32_paths(err, A):
     assert np.all(err <= bound)
 
 
-def test_fp32_paths_small_workload(pm, ctx, orc):
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+def test_fp32_paths_small_workload(pm, ctx, orc, engine_of, engine):
+    engine_of(engine)
     wl = W.time_small()
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
     m, v, ep = prob.observe_time(wl.u, wl.obs, wl.kappa, wl.T, wl.dt, wl.n_particles, wl.seed, endpoints=True)
@@ -208,7 +226,9 @@ def test_fp32_paths_small_workload(pm, ctx, orc):
     assert np.all(np.abs(np_(m) - pay.mean(axis=1)) <= 4 * se + 1e-12)
 
 
-def test_fp32_short_horizon_paths_main_workload(pm, ctx, orc):
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+def test_fp32_short_horizon_paths_main_workload(pm, ctx, orc, engine_of, engine):
+    engine_of(engine)
     wl = W.time_main()
     T = 25 * wl.dt
     Np = 256
@@ -222,7 +242,9 @@ def test_fp32_short_horizon_paths_main_workload(pm, ctx, orc):
     check_fp32_paths(err[:8, :32], A)
 
 
-def test_fp32_zero_flow_full_horizon(pm, ctx, orc):
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+def test_fp32_zero_flow_full_horizon(pm, ctx, orc, engine_of, engine):
+    engine_of(engine)
     wl = W.time_main()
     u0 = np.zeros_like(wl.u)
     Np = 200
@@ -233,9 +255,11 @@ def test_fp32_zero_flow_full_horizon(pm, ctx, orc):
     assert np.max(tdist(np_(ep), ep_ref)) <= 1e-5
 
 
-def test_fp32_means_main_workload_paired(pm, ctx, orc):
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+def test_fp32_means_main_workload_paired(pm, ctx, orc, engine_of, engine):
     """Main workload (49 points, 1000 steps), 512 particles per point: the
     per-path endpoints have decorrelated by T = 1, so this is the 3-SE test."""
+    engine_of(engine)
     wl = W.time_main()
     Np = 512
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
@@ -251,9 +275,11 @@ def test_fp32_means_main_workload_paired(pm, ctx, orc):
     assert np.sum(z > 3) <= 2 and np.all(z < 4.5), z
 
 
-def test_full_size_means_against_oracle_subsample(pm, ctx, orc):
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+def test_full_size_means_against_oracle_subsample(pm, ctx, orc, engine_of, engine):
     """Main workload at full size (49 x 1e5 x 1000) in the benchmark's launch
     configuration; the oracle runs the first 400 particles of every point."""
+    engine_of(engine)
     wl = W.time_main()
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
     m, v = prob.observe_time(wl.u, wl.obs, wl.kappa, wl.T, wl.dt, wl.n_particles, wl.seed)
@@ -270,9 +296,10 @@ def test_full_size_means_against_oracle_subsample(pm, ctx, orc):
 # determinism, batching, edge cases
 # ---------------------------------------------------------------------------
 
-def test_bitwise_identical_across_launch_shapes(pm, ctx):
+def test_bitwise_identical_across_launch_shapes(pm, ctx, engine_of):
     wl = W.time_main()
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+    engine_of("valu")
     res = []
     for ppl, src in ((1, 0), (2, 0), (3, 0), (4, 0), (1, 1), (2, 1), (3, 1), (4, 1)):
         ctx.set_tuning(ppl, src)
@@ -282,9 +309,21 @@ def test_bitwise_identical_across_launch_shapes(pm, ctx):
     m0, v0 = prob.observe_time(wl.u, wl.obs, wl.kappa, 0.2, wl.dt, 3000, wl.seed)
     for m, v in res:
         assert np.array_equal(m, np_(m0)) and np.array_equal(v, np_(v0))
+    # the matrix-core engine: persistent grids of 1, 2, 3 blocks per CU and
+    # the occupancy limit
+    engine_of("mfma")
+    res = []
+    for bpc in (1, 2, 3, 0):
+        ctx.set_blocks_per_cu(bpc)
+        m, v = prob.observe_time(wl.u, wl.obs, wl.kappa, 0.2, wl.dt, 3000, wl.seed)
+        res.append((np_(m), np_(v)))
+    for m, v in res[:-1]:
+        assert np.array_equal(m, res[-1][0]) and np.array_equal(v, res[-1][1])
 
 
-def test_batch_equals_separate_calls_bitwise(pm, ctx):
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+def test_batch_equals_separate_calls_bitwise(pm, ctx, engine_of, engine):
+    engine_of(engine)
     wl = W.batch_main(n_u=5, lo=50, hi=3000)
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
     T = 0.1
