@@ -282,10 +282,13 @@ int pm_set_tuning(pm_ctx *ctx, int particles_per_lane, int coef_source);
  *     near 1e-6 of max |v|, paths within the FP32 error contract);
  *   PM_ENGINE_VALU: FP32 fused multiply-adds on the vector units (the
  *     kernel that pm_set_tuning and pm_autotune_time tune).
- * The two engines round differently, so their results agree to that
- * contract, not bit for bit; each is deterministic.  FP64 problems, other
- * domains and K > PM_MAX_K_MX ignore the setting.  Returns PM_EINVAL for
- * another value or a closed context. */
+ * The matrix-core kernels keep particle coordinates as 32-bit fractions of
+ * the period (resolution 2^-32, the wrap by modular overflow) and apply when
+ * sqrt(2 kappa dt) <= 0.05; larger steps run on the vector units.  The two
+ * engines round differently, so their results agree to that contract, not
+ * bit for bit; each is deterministic.  FP64 problems, other domains and
+ * K > PM_MAX_K_MX ignore the setting.  Returns PM_EINVAL for another value
+ * or a closed context. */
 int pm_set_time_engine(pm_ctx *ctx, int engine);
 
 /* Coefficient source of the Dirichlet walk: 0 = LDS, 1 = scalar cache

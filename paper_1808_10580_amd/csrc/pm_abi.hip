@@ -178,6 +178,20 @@ StepConsts<T> step_consts(double dt, double kappa)
     return c;
 }
 
+// The same constants in units of 2^-32 of the period, for the fixed-point
+// coordinates of the small-K matrix-core kernels.
+StepConsts<float> fixed_consts(double dt, double kappa)
+{
+    const double S = 4294967296.0;
+    StepConsts<float> c;
+    c.dth = (float)(dt * S);
+    c.dtl = (float)(dt * S - (double)c.dth);
+    c.sq = (float)(std::sqrt(2.0 * kappa * dt) * S);
+    return c;
+}
+
+bool mx_step_ok(double dt, double kappa) { return std::sqrt(2.0 * kappa * dt) <= MX_MAX_SIGMA; }
+
 template <typename T>
 int fold(pm_ctx *c, const pm_problem *p, const double *u, int n_sets, int64_t u_stride, T **coef_out,
          int64_t *stride_out)
@@ -401,7 +415,7 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
                                    endpoints);
     }
     bool mx = false;
-    if constexpr (std::is_same<T, float>::value) mx = use_mx(c, p);
+    if constexpr (std::is_same<T, float>::value) mx = use_mx(c, p) && mx_step_ok(dte, kappa);
     T *coef = nullptr;
     int64_t cstride = 0;
     const unsigned char *mx_sets = nullptr;
@@ -521,6 +535,7 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
         if (mx) {
             MxTimeArgs ma{};
             ma.t = a;
+            ma.fx = fixed_consts(dte, kappa);
             ma.sets = mx_sets;
             le = launch_time_mx(ma, p->K, c->n_cu, c->bpc, c->stream);
         } else {
@@ -1102,7 +1117,7 @@ static int step_mx(pm_ctx *c, const pm_problem *p, const double *u, int64_t coun
     a.i = i;
     a.j = j;
     a.seed = seed;
-    a.sc = step_consts<float>(dt, kappa);
+    a.fx = fixed_consts(dt, kappa);
     a.v0x = (float)p->v0[0];
     a.v0y = (float)p->v0[1];
     a.Y = Y;
@@ -1122,7 +1137,8 @@ int pm_step(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, cons
     if (!(std::isfinite(kappa) && kappa >= 0.0) || !finite_pos(dt)) return PM_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
     if (p->hk) return step_hk(c, p, u, count, X, n, i, j, kappa, dt, seed, Y, nullptr);
-    if (use_mx(c, p)) return step_mx(c, p, u, count, X, n, i, j, kappa, dt, seed, Y, nullptr);
+    if (use_mx(c, p) && mx_step_ok(dt, kappa))
+        return step_mx(c, p, u, count, X, n, i, j, kappa, dt, seed, Y, nullptr);
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);
         T *coef;

@@ -28,8 +28,15 @@ struct MxPackArgs {
     int row_stride;
 };
 
+// Particle coordinates of the small-K kernels are 32-bit fractions of the
+// period (position = X 2^-32); their step constants come pre-scaled by 2^32.
+// Usable while one step moves a particle by far less than half the period:
+// the C ABI takes this engine only for sqrt(2 kappa dt) <= MX_MAX_SIGMA.
+constexpr double MX_MAX_SIGMA = 0.05;
+
 struct MxTimeArgs {
-    TimeArgs<float> t;           // chunk layout, steps, readouts, outputs (t.coef unused)
+    TimeArgs<float> t;           // chunk layout, steps, readouts, outputs (t.coef, t.sc unused)
+    StepConsts<float> fx;        // dt (hi + lo) and sqrt(2 kappa dt), each x 2^32
     const unsigned char *sets;   // [n_u][MX_SET_BYTES]
 };
 
@@ -41,7 +48,7 @@ struct MxStepArgs {
     const uint32_t *i;
     const uint32_t *j;
     uint64_t seed;
-    StepConsts<float> sc;
+    StepConsts<float> fx;  // dt (hi + lo) and sqrt(2 kappa dt), each x 2^32
     float v0x, v0y;
     double *Y;  // step mode
     double *V;  // velocity mode when non-null (n, i, j, Y unused)

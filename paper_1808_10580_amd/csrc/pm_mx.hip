@@ -220,6 +220,32 @@ __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, fl
     vy = (ay0 + ay1) * inv;
 }
 
+// ---------------------------------------------------------------------------
+// Torus coordinate as a 32-bit fraction of the period, position = X 2^-32:
+// the wrap is the modular overflow of the update.  The increment
+// -v dt + sqrt(2 kappa dt) z of eq. (euler) is formed in FP32 in units of
+// 2^-32 (constants pre-scaled by 2^32, dt split hi + lo so that its rounding
+// adds no coherent drift) and rounded to the nearest unit: 2.3e-10 per step,
+// below the FP32 velocity error.  The velocity is evaluated at the FP32 value
+// of the position in [-1/2, 1/2).
+// ---------------------------------------------------------------------------
+struct FixCoord {
+    uint32_t X;
+    __device__ __forceinline__ void set(double x)
+    {
+        const double f = x - floor(x);  // [0, 1); 2^32 wraps to 0 below
+        X = (uint32_t)(uint64_t)llrint(f * 4294967296.0);
+    }
+    __device__ __forceinline__ float at() const { return (float)(int32_t)X * 0x1p-32f; }
+    __device__ __forceinline__ double value() const { return (double)(int32_t)X * 0x1p-32; }
+    __device__ __forceinline__ void advance(float vel, float z, const StepConsts<float> &c)
+    {
+        float d = __builtin_fmaf(-c.dtl, vel, c.sq * z);
+        d = __builtin_fmaf(-c.dth, vel, d);
+        X += (uint32_t)(int32_t)__builtin_rintf(d);
+    }
+};
+
 __device__ __forceinline__ void load_set(const unsigned char *__restrict__ set, int lane, h16x8 &ahi, h16x8 &alo,
                                          float &inv)
 {
@@ -279,17 +305,15 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
         const uint32_t pi = (uint32_t)i, pj = (uint32_t)j;
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 
-        Coord<float> x, y;
+        FixCoord x, y;
         x.set(a.obs[2 * j]);
         y.set(a.obs[2 * j + 1]);
 
         auto step = [&](float z0, float z1) {
             float vx, vy;
             mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy);
-            x.advance(vx + a.v0x, z0, a.sc);
-            y.advance(vy + a.v0y, z1, a.sc);
-            x.wrap();
-            y.wrap();
+            x.advance(vx + a.v0x, z0, m.fx);
+            y.advance(vy + a.v0y, z1, m.fx);
         };
         int r = 0;
         int64_t next = a.read_at[0];
@@ -340,7 +364,7 @@ __global__ __launch_bounds__(256) void k_step_mx(const MxStepArgs a)
     h16x8 ahi, alo;
     float inv;
     load_set(a.set, lane, ahi, alo, inv);
-    Coord<float> x, y;
+    FixCoord x, y;
     x.set(act ? a.X[2 * e] : 0.0);
     y.set(act ? a.X[2 * e + 1] : 0.0);
     float vx, vy;
@@ -356,8 +380,8 @@ __global__ __launch_bounds__(256) void k_step_mx(const MxStepArgs a)
     float z0, z1;
     if ((n & 1) == 0) box_muller(w.x, w.y, z0, z1);
     else box_muller(w.z, w.w, z0, z1);
-    x.advance(vx + a.v0x, z0, a.sc);
-    y.advance(vy + a.v0y, z1, a.sc);
+    x.advance(vx + a.v0x, z0, a.fx);
+    y.advance(vy + a.v0y, z1, a.fx);
     double nx = x.value(), ny = y.value();
     nx -= floor(nx);
     ny -= floor(ny);
