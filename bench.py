@@ -38,9 +38,10 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 # reported when the sources still hash to the recorded value, else null.
 # Per velocity engine: (bytes per launch, SHA-256 of the kernel's sources).
 COUNTER_TRAFFIC = {
-    # FETCH 163.25 KiB x 2 + WRITE 77,480.78 KiB x 1
-    "valu": (79_674_656, "07d7dbb6588befae6b41407d7750db1ba9c289cf31081fd4d6e49d1a8c6c8f6e"),
-    "mfma": (None, None),
+    # k_time<float,6,3>: FETCH 164.44 KiB x 2 + WRITE 77,480.78 KiB x 1
+    "valu": (79_677_088, "8b10e57c6dce9afde4afa80eca8b44c376325c8b25fd1cc6dd045b05e78faab5"),
+    # k_time_mx<6>: FETCH 66.56 KiB x 2 + WRITE 79,172.34 KiB x 1
+    "mfma": (81_208_800, "bc2b7d0f968032e7516bfffcf59b964655b11843a9119db6a2d406ea4a04bd95"),
 }
 KERNEL_SOURCES = {
     "valu": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
