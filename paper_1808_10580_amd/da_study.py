@@ -1,6 +1,7 @@
 """Plain pCN vs delayed-acceptance pCN with the learned surrogate.
 
     python -m paper_1808_10580_amd.da_study [--n-train 8192] [--train-particles 10000] [--iters 2000]
+                                            [--horizon T] [--engine auto|valu]
 
 Setting (the surrogate workload): the main torus problem (168 coefficients,
 49 observation points, T = 1), synthetic data y = G(u*) + N(0, gamma^2),
@@ -16,6 +17,10 @@ draws only learns the prior mean of G; the training inputs are pCN moves of
 size 2 beta around the pilot chain's states (where the chains live), their
 outputs the batched particle map at a reduced particle count.
 
+--horizon sets the observation time (default the workload's T = 1, where the
+flow has mixed the particles far apart); shorter horizons give a smoother,
+less chaotic G.  --engine selects the FP32 velocity engine of the particle map.
+
 Three chains: plain pCN, delayed acceptance with the surrogate misfit at the
 data noise gamma, and delayed acceptance with an approximation-error model
 (stage-1 noise gamma^2 + sigma_j^2, sigma_j the surrogate's held-out error per
@@ -27,6 +32,7 @@ time and held-out error.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import time
@@ -35,7 +41,7 @@ import numpy as np
 
 
 def run(n_train=8192, train_particles=10_000, iters=2000, pilot=60, chain_particles=100_000, seed=1808,
-        epochs=200, verbose=True, dump=None, dataset_only=False):
+        epochs=200, verbose=True, dump=None, dataset_only=False, horizon=None, engine="auto"):
     import torch
 
     import paper_1808_10580_amd as pm
@@ -45,14 +51,18 @@ def run(n_train=8192, train_particles=10_000, iters=2000, pilot=60, chain_partic
 
     setup = W.surrogate_setup(seed)
     wl = setup["base"]
+    if horizon is not None:
+        wl = dataclasses.replace(wl, T=float(horizon))
     gamma = setup["gamma"]
     std = W.prior_std(wl.modes)
     prior_std = np.concatenate([std, std])
     ctx = pm.Context(0)
+    ctx.set_time_engine(engine)
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
-    prob.autotune_time(wl.u, wl.obs, wl.kappa, wl.dt, chain_particles, wl.seed, n_probe_steps=50)
+    if engine == "valu":
+        prob.autotune_time(wl.u, wl.obs, wl.kappa, wl.dt, chain_particles, wl.seed, n_probe_steps=50)
     out = {"n_train": n_train, "train_particles": train_particles, "chain_particles": chain_particles,
-           "iters": iters, "gamma": gamma}
+           "iters": iters, "gamma": gamma, "horizon": wl.T, "engine": engine}
 
     # data y = G(u*) + gamma eta
     fwd = mcmc.ParticleForward(prob, wl, chain_particles, wl.seed)
@@ -149,9 +159,11 @@ def main():
     ap.add_argument("--epochs", type=int, default=200)
     ap.add_argument("--dump", default=None, help="save the training set (npz) here")
     ap.add_argument("--dataset-only", action="store_true", help="stop after the training set")
+    ap.add_argument("--horizon", type=float, default=None, help="observation time T (default: the workload's)")
+    ap.add_argument("--engine", default="auto", choices=["auto", "valu", "mfma"])
     a = ap.parse_args()
     print(json.dumps(run(a.n_train, a.train_particles, a.iters, epochs=a.epochs, dump=a.dump,
-                         dataset_only=a.dataset_only)))
+                         dataset_only=a.dataset_only, horizon=a.horizon, engine=a.engine)))
 
 
 if __name__ == "__main__":
