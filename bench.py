@@ -72,9 +72,10 @@ def counter_traffic(engine: str):
     return nbytes
 
 
-def engine_in_use(pm, engine_arg: str, K: int) -> str:
-    """The velocity engine the library runs for an FP32 torus problem."""
-    if engine_arg == "valu" or not (1 <= K <= pm.MAX_K_MX):
+def engine_in_use(pm, engine_arg: str, K: int, domain: str = "torus") -> str:
+    """The velocity engine the library runs for an FP32 torus or disk problem."""
+    limit = pm.MAX_K_MX if domain == "torus" else pm.MAX_K_DISK_MX
+    if engine_arg == "valu" or not (1 <= K <= limit):
         return "valu"
     return "mfma"
 
@@ -173,7 +174,7 @@ def bench_other(args):
 
     dev = torch.device("cuda", 0)
     ctx = pm.Context(0)
-    ctx.set_time_engine(args.engine)
+    ctx.set_velocity_engine(args.engine)
     name = args.workload
     cpu = None
     if name == "torus-k80-turbulent":
@@ -221,8 +222,10 @@ def bench_other(args):
             last["steps"] = float((tau / wl.dt).sum() * wl.n_particles)
         K = int(abs(wl.modes).max())
         fl = flops_per_particle_step_disk(K)
-        rl = {"bound": "alu", "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "kernel": f"k_dirichlet<float,{K}>",
-              "flop_per_particle_step": fl}
+        eng = engine_in_use(pm, args.engine, K, "disk")
+        rl = {"bound": "alu", "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+              "kernel": f"k_dirichlet_mx<{K}>" if eng == "mfma" else f"k_dirichlet<float,{K}>",
+              "flop_per_particle_step": fl, "velocity_engine": eng}
         desc = ("disk-dirichlet: unit disk, 64-coefficient stream function x (1-r^2)^2, kappa=0.02, g=cos 3phi, "
                 "f=-1, 25 points x 5e4 particles, dt=1e-4, walks until exit, FP32 states + FP64 exit test")
     elif name == "torus-k6-batch":
@@ -306,7 +309,7 @@ def main():
     dev = torch.device("cuda", 0)
     ctx = pm.Context(0)
     ctx.set_tuning(args.ppl, args.coef_source)
-    ctx.set_time_engine(args.engine)
+    ctx.set_velocity_engine(args.engine)
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
     u = torch.tensor(wl.u, dtype=torch.float64, device=dev)
     obs = torch.tensor(wl.obs, dtype=torch.float64, device=dev)

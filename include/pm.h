@@ -102,11 +102,13 @@ typedef struct {
  * regime of Section 4's turbulent example, |k|_2 <= 80 (20,081 modes). */
 #define PM_MAX_K_MFMA 95
 /* FP32 torus problems with 1 <= K <= PM_MAX_K_MX (B = 2K + 1 <= 15 basis
- * functions per axis) run the same bilinear forms on the matrix cores by
- * default (engine PM_ENGINE_AUTO; see pm_set_time_engine). */
+ * functions per axis) and FP32 disk problems with 1 <= K <= PM_MAX_K_DISK_MX
+ * run the same bilinear forms on the matrix cores by default (engine
+ * PM_ENGINE_AUTO; see pm_set_velocity_engine). */
 #define PM_MAX_K_MX 7
+#define PM_MAX_K_DISK_MX 4
 
-/* Velocity engines of the FP32 torus time path (pm_set_time_engine). */
+/* Velocity engines of FP32 problems (pm_set_velocity_engine). */
 #define PM_ENGINE_AUTO 0 /* matrix cores where they apply (K <= PM_MAX_K_MX), else vector units */
 #define PM_ENGINE_VALU 1 /* vector units: FP32 fused multiply-adds */
 #define PM_ENGINE_MFMA 2 /* matrix cores where they apply (the same as AUTO) */
@@ -272,24 +274,27 @@ const char *pm_strerror(int status);
  * Every choice gives bitwise identical results. */
 int pm_set_tuning(pm_ctx *ctx, int particles_per_lane, int coef_source);
 
-/* Velocity engine of the FP32 torus time problem (Algorithm 1, eq. euler
- * with the field of eq. v_expand), used by pm_observe_time, _multi, _batch,
- * pm_jacobian_time, the graphs and pm_step / pm_velocity:
- *   PM_ENGINE_AUTO (default) or PM_ENGINE_MFMA: for 1 <= K <= PM_MAX_K_MX
- *     the two bilinear forms of 64 particles are one matrix-core contraction
- *     (v_mfma_f32_32x32x16_f16 on coefficients and x basis split into FP16
- *     hi + lo halves, three products, FP32 accumulation: velocity errors
- *     near 1e-6 of max |v|, paths within the FP32 error contract);
+/* Velocity engine (eq. v_expand) of FP32 problems:
+ *   PM_ENGINE_AUTO (default) or PM_ENGINE_MFMA: on the torus with
+ *     1 <= K <= PM_MAX_K_MX (Algorithm 1: pm_observe_time, _multi, _batch,
+ *     pm_jacobian_time, the graphs) and on the disk with 1 <= K <= PM_MAX_K_DISK_MX
+ *     (Algorithm 2: pm_observe_dirichlet), and in pm_step / pm_velocity for
+ *     both, the bilinear forms of 64 particles are one matrix-core
+ *     contraction (v_mfma_f32_32x32x16_f16 on coefficients and x basis
+ *     split into FP16 hi + lo halves, three products, FP32 accumulation:
+ *     velocity errors near 5e-7 of max |v|, paths within the FP32 error
+ *     contract);
  *   PM_ENGINE_VALU: FP32 fused multiply-adds on the vector units (the
  *     kernel that pm_set_tuning and pm_autotune_time tune).
- * The matrix-core kernels keep particle coordinates as 32-bit fractions of
- * the period (resolution 2^-32, the wrap by modular overflow) and apply when
- * sqrt(2 kappa dt) <= 0.05; larger steps run on the vector units.  The two
- * engines round differently, so their results agree to that contract, not
- * bit for bit; each is deterministic.  FP64 problems, other domains and
- * K > PM_MAX_K_MX ignore the setting.  Returns PM_EINVAL for another value
- * or a closed context. */
-int pm_set_time_engine(pm_ctx *ctx, int engine);
+ * On the torus the matrix-core kernels keep particle coordinates as 32-bit
+ * fractions of the period (resolution 2^-32, the wrap by modular overflow)
+ * and apply when sqrt(2 kappa dt) <= 0.05; larger steps run on the vector
+ * units.  On the disk they keep the vector engine's double-float
+ * coordinates.  The two engines round differently, so their results agree
+ * to that contract, not bit for bit; each is deterministic.  FP64 problems,
+ * the square and larger K ignore the setting.  Returns PM_EINVAL for another
+ * value or a closed context. */
+int pm_set_velocity_engine(pm_ctx *ctx, int engine);
 
 /* Coefficient source of the Dirichlet walk: 0 = LDS, 1 = scalar cache
  * (default).  Both give bitwise identical results. */

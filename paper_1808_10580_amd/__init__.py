@@ -29,6 +29,7 @@ FIELD_KINDS = {"zero": 0, "const": 1, "sinsin": 2, "fourier": 3, "gauss_periodic
 MAX_SOURCES = 4
 MAX_K = 8
 MAX_K_MX = 7  # FP32 torus problems with 1 <= K <= MAX_K_MX use the matrix cores by default
+MAX_K_DISK_MX = 4  # the same for FP32 disk problems
 ENGINES = {"auto": 0, "valu": 1, "mfma": 2}
 
 
@@ -76,7 +77,7 @@ def _declare(L):
     L.pm_destroy.restype = None
     L.pm_set_stream.argtypes = [_vp, _vp]
     L.pm_set_tuning.argtypes = [_vp, C.c_int, C.c_int]
-    L.pm_set_time_engine.argtypes = [_vp, C.c_int]
+    L.pm_set_velocity_engine.argtypes = [_vp, C.c_int]
     L.pm_problem_create.argtypes = [_vp, C.POINTER(_vp), C.c_int, C.c_int, _vp, _vp,
                                     C.POINTER(_Field), C.c_int]
     L.pm_problem_destroy.argtypes = [_vp]
@@ -191,12 +192,12 @@ class Context:
     def set_tuning(self, particles_per_lane: int = 0, coef_source: int = 0):
         _check(_lib().pm_set_tuning(self.h, particles_per_lane, coef_source), "pm_set_tuning")
 
-    def set_time_engine(self, engine="auto"):
-        """Velocity engine of the FP32 torus time path: "auto"/"mfma" (matrix
-        cores for 1 <= K <= 7) or "valu" (vector FMAs; the kernel that
-        set_tuning and autotune_time tune)."""
+    def set_velocity_engine(self, engine="auto"):
+        """Velocity engine of FP32 problems: "auto"/"mfma" (matrix cores for
+        torus 1 <= K <= 7 and disk 1 <= K <= 4) or "valu" (vector FMAs; the
+        kernel that set_tuning and autotune_time tune)."""
         code = ENGINES[engine] if isinstance(engine, str) else int(engine)
-        _check(_lib().pm_set_time_engine(self.h, code), "pm_set_time_engine")
+        _check(_lib().pm_set_velocity_engine(self.h, code), "pm_set_velocity_engine")
 
     def set_dirichlet_source(self, coef_source: int = 1):
         _check(_lib().pm_set_dirichlet_source(self.h, coef_source), "pm_set_dirichlet_source")

@@ -239,11 +239,16 @@ int fold_hk(pm_ctx *c, const pm_problem *p, const double *u, int n_sets, int64_t
 }
 
 // The small-K matrix-core velocity serves FP32 torus problems with
-// 1 <= K <= MX_MAX_K unless the vector engine is requested.
+// 1 <= K <= MX_MAX_K and FP32 disk problems with 1 <= K <= MX_MAX_K_DISK
+// unless the vector engine is requested.
+static_assert(PM_MAX_K_MX == MX_MAX_K && PM_MAX_K_DISK_MX == MX_MAX_K_DISK, "engine limits in pm.h");
+
 bool use_mx(const pm_ctx *c, const pm_problem *p)
 {
-    return c->engine != PM_ENGINE_VALU && p->domain == PM_TORUS && p->prec == PM_FP32 && !p->hk && p->K >= 1 &&
-           p->K <= MX_MAX_K;
+    if (c->engine == PM_ENGINE_VALU || p->prec != PM_FP32 || p->hk || p->K < 1) return false;
+    if (p->domain == PM_TORUS) return p->K <= MX_MAX_K;
+    if (p->domain == PM_DISK) return p->K <= MX_MAX_K_DISK;
+    return false;
 }
 
 // FP64 fold, then the split-FP16 operands of the small-K matrix-core path.
@@ -261,6 +266,7 @@ int fold_mx(pm_ctx *c, const pm_problem *p, const double *u, int n_sets, int64_t
     pa.coef_stride = cs;
     pa.K = p->K;
     pa.row_stride = row_stride(p->domain, p->K);
+    pa.domain = p->domain;
     if (launch_pack_mx(pa, (unsigned char *)c->mx, n_sets, c->stream) != hipSuccess) return PM_EDEVICE;
     *out = (const unsigned char *)c->mx;
     return PM_OK;
@@ -573,9 +579,14 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
                            double *tau_mean, double *tau_var, int64_t *n_capped, double *paths,
                            int n_src = 0, const double *src = nullptr, double *src_mean = nullptr)
 {
-    T *coef;
-    int64_t cstride;
-    int st = fold<T>(c, p, u, 1, 2 * (int64_t)p->n_modes, &coef, &cstride);
+    // the disk's FP32 walk runs the matrix-core velocity where it applies
+    bool mx = false;
+    if constexpr (std::is_same<T, float>::value) mx = p->domain == PM_DISK && n_src == 0 && use_mx(c, p);
+    T *coef = nullptr;
+    int64_t cstride = 0;
+    const unsigned char *mx_set = nullptr;
+    int st = mx ? fold_mx(c, p, u, 1, 2 * (int64_t)p->n_modes, &mx_set)
+                : fold<T>(c, p, u, 1, 2 * (int64_t)p->n_modes, &coef, &cstride);
     if (st) return st;
     const int64_t total = np * n_obs;
     if ((st = ensure(c, &c->pay, &c->pay_cap, total * sizeof(double)))) return st;
@@ -664,17 +675,20 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     a.mode = 0;
     a.dump_below = n_follow > 0 ? c->dir_dump : 0;
     a.pout = pools[0];
-    if (launch_dirichlet<T>(a, p->K, fk, c->dir_src, c->n_cu, c->dir_bpc, p->domain, c->stream) != hipSuccess)
-        return PM_EDEVICE;
+    auto launch = [&]() -> hipError_t {
+        if constexpr (std::is_same<T, float>::value) {
+            if (mx) return launch_dirichlet_mx(a, mx_set, p->K, fk, c->n_cu, c->dir_bpc, c->stream);
+        }
+        return launch_dirichlet<T>(a, p->K, fk, c->dir_src, c->n_cu, c->dir_bpc, p->domain, c->stream);
+    };
+    if (launch() != hipSuccess) return PM_EDEVICE;
     for (int r = 1; r <= n_follow; ++r) {
         a.mode = 1;
         a.pin = pools[(r - 1) & 1];
         a.pout = pools[r & 1];
         a.dump_below = r < n_follow ? c->dir_dump : 0;
         if (launch_pool_reset(a.pin.head, a.pout.count, c->stream) != hipSuccess) return PM_EDEVICE;
-        if (launch_dirichlet<T>(a, p->K, fk, c->dir_src, c->n_cu, c->dir_bpc, p->domain, c->stream) !=
-            hipSuccess)
-            return PM_EDEVICE;
+        if (launch() != hipSuccess) return PM_EDEVICE;
     }
     PM_HIP(hipEventRecord(c->ev1, c->stream));
     c->timed = true;
@@ -819,7 +833,7 @@ int pm_set_tuning(pm_ctx *c, int ppl, int src)
     return PM_OK;
 }
 
-int pm_set_time_engine(pm_ctx *c, int engine)
+int pm_set_velocity_engine(pm_ctx *c, int engine)
 {
     if (!c || c->closed) return PM_EINVAL;
     if (engine != PM_ENGINE_AUTO && engine != PM_ENGINE_VALU && engine != PM_ENGINE_MFMA) return PM_EINVAL;
@@ -1118,11 +1132,12 @@ static int step_mx(pm_ctx *c, const pm_problem *p, const double *u, int64_t coun
     a.j = j;
     a.seed = seed;
     a.fx = fixed_consts(dt, kappa);
+    a.sc = step_consts<float>(dt, kappa);
     a.v0x = (float)p->v0[0];
     a.v0y = (float)p->v0[1];
     a.Y = Y;
     a.V = V;
-    return launch_step_mx(a, p->K, c->stream) == hipSuccess ? PM_OK : PM_EDEVICE;
+    return launch_step_mx(a, p->K, p->domain, c->stream) == hipSuccess ? PM_OK : PM_EDEVICE;
 }
 
 int pm_step(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, const double *X,
@@ -1137,7 +1152,7 @@ int pm_step(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, cons
     if (!(std::isfinite(kappa) && kappa >= 0.0) || !finite_pos(dt)) return PM_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
     if (p->hk) return step_hk(c, p, u, count, X, n, i, j, kappa, dt, seed, Y, nullptr);
-    if (use_mx(c, p) && mx_step_ok(dt, kappa))
+    if (use_mx(c, p) && (p->domain == PM_DISK || mx_step_ok(dt, kappa)))
         return step_mx(c, p, u, count, X, n, i, j, kappa, dt, seed, Y, nullptr);
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);

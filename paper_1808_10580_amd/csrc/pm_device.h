@@ -82,6 +82,14 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double &z0,
     z1 = r * s;
 }
 
+// A 64-bit value that is the same in every lane, as a scalar (SGPR) value.
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // sin/cos of 2 pi s.
 __device__ __forceinline__ void sincos_rev(float s, float &sn, float &cs)
 {

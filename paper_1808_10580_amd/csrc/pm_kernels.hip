@@ -15,6 +15,7 @@
 //                  fixed order with compensated sums
 //   k_step, k_velocity, k_normals   replay / inspection hooks
 #include "pm_kernels.h"
+#include "pm_walk.h"
 
 namespace pm {
 
@@ -87,13 +88,6 @@ __global__ __launch_bounds__(256) void k_fold(FoldArgs a, T *__restrict__ coef)
 // ---------------------------------------------------------------------------
 // Wave-level helpers.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t uniform64(int64_t v)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -342,22 +336,6 @@ __global__ __launch_bounds__(256) void k_time_payoff(const PayArgs a)
     }
 }
 
-// ---------------------------------------------------------------------------
-// Algorithm 2 on the unit disk, persistent lanes.
-// Each lane walks one particle at a time; a lane whose particle has left the
-// disk takes the next particle index from a device queue (one atomic per wave
-// per refill).  Refills happen only at even step counts so that all lanes of
-// a wave consume the two normal pairs of one Philox block together.
-// FK = 0: source f = p0 x + p1 y + p2 (zero, constant, linear) inline;
-// FK = 1: any field kind.
-// ---------------------------------------------------------------------------
-template <int FK>
-__device__ __forceinline__ double source_at(const FieldArg &f, double x, double y)
-{
-    if constexpr (FK == 0) return __builtin_fma(f.p[0], x, __builtin_fma(f.p[1], y, f.p[2]));
-    else return field_eval(f, x, y);
-}
-
 template <typename T, int K, int FK, bool SC, int DOM>
 __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
 {
@@ -369,40 +347,10 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
         for (int e = threadIdx.x; e < NC; e += blockDim.x) lds[e] = a.coef[e];
         __syncthreads();
     }
-
-    const int lane = threadIdx.x & 63;
-    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    bool has = false, done = false;
-    Coord<T> x, y;
-    x.set(0.0);
-    y.set(0.0);
-    double I = 0.0;
-    double Is[FK == 2 ? PM_MAX_SOURCES : 1];  // per-source integrals (FK = 2)
-#pragma unroll
-    for (int q = 0; q < (FK == 2 ? PM_MAX_SOURCES : 1); ++q) Is[q] = 0.0;
-    int64_t n = 0, t = 0;
-    uint32_t pi = 0, pj = 0;
-
-    auto finish = [&](double ex, double ey, bool exited) {
-        a.exitp[2 * t] = ex;
-        a.exitp[2 * t + 1] = ey;
-        a.integ[t] = I;
-        a.nsteps[t] = (double)n;
-        a.capped[t] = exited ? 0 : 1;
-        if constexpr (FK == 2) {
-#pragma unroll
-            for (int q = 0; q < PM_MAX_SOURCES; ++q)
-                if (q < a.n_src) a.integ_src[q * a.total + t] = Is[q];
-        }
-        has = false;
-    };
-
-    auto substep = [&](T z0, T z1) {
+    dirichlet_walk<T, FK, DOM>(a, [&](T xa, T ya, T &vx, T &vy) {
         T phx[B], phy[B];
-        const T xa = x.at(), ya = y.at();
         trig_basis<T, K>(xa, phx);
         trig_basis<T, K>(ya, phy);
-        T vx, vy;
         // coefficients re-read every step: scalar cache (SGPR operands) or LDS
         if constexpr (DOM == PM_DISK) {
             if constexpr (SC) {
@@ -424,125 +372,7 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
             vx = ax[0];
             vy = ay[0];
         }
-        Coord<T> nx = x, ny = y;
-        nx.advance(vx + a.v0x, z0, a.sc);
-        ny.advance(vy + a.v0y, z1, a.sc);
-        if (has) {
-            const double xd = x.value(), yd = y.value();
-            if constexpr (FK == 2) {  // left point, one integral per Gaussian source
-#pragma unroll
-                for (int q = 0; q < PM_MAX_SOURCES; ++q) {
-                    if (q < a.n_src) {
-                        const double dx = xd - a.src[q][0], dy = yd - a.src[q][1];
-                        Is[q] += exp(-a.src[q][2] * (dx * dx + dy * dy)) * a.dtd;
-                    }
-                }
-            } else {
-                I += source_at<FK>(a.f, xd, yd) * a.dtd;  // left point
-            }
-            n += 1;
-            const double nxd = nx.value(), nyd = ny.value();
-            bool out;
-            if constexpr (DOM == PM_DISK) out = nxd * nxd + nyd * nyd >= 1.0;
-            else out = !(nxd > 0.0 && nxd < 1.0 && nyd > 0.0 && nyd < 1.0);
-            if (out) {
-                // exit point: the nearest boundary point (radial projection
-                // onto the circle; clamping onto the square)
-                if constexpr (DOM == PM_DISK) {
-                    const double r = sqrt(nxd * nxd + nyd * nyd);
-                    finish(nxd / r, nyd / r, true);
-                } else {
-                    finish(fmin(fmax(nxd, 0.0), 1.0), fmin(fmax(nyd, 0.0), 1.0), true);
-                }
-            } else if (n >= a.max_steps) {
-                finish(nxd, nyd, false);
-            } else {
-                x = nx;
-                y = ny;
-            }
-        }
-    };
-
-    // input: fresh particles (mode 0) or saved walkers (mode 1)
-    unsigned long long *const qhead = a.mode ? a.pin.head : a.queue;
-    const int64_t limit = a.mode ? (int64_t)uniform64((int64_t)*a.pin.count) : a.total;
-    int iters = 0;
-    for (;;) {
-        const bool need = !has && !done;
-        const unsigned long long m = __ballot(need);
-        if (m) {
-            const int first = __ffsll((long long)m) - 1;
-            unsigned long long base = 0;
-            if (lane == first) base = atomicAdd(qhead, (unsigned long long)__popcll(m));
-            base = __shfl(base, first);
-            if (need) {
-                const int rank = __popcll(m & ((1ull << lane) - 1ull));
-                const int64_t tt = (int64_t)base + rank;
-                if (tt < limit) {
-                    if (a.mode == 0) {
-                        const int64_t jq = tt / a.np;
-                        pj = (uint32_t)a.order[jq];
-                        pi = (uint32_t)(tt - jq * a.np);
-                        x.set(a.obs[2 * pj]);
-                        y.set(a.obs[2 * pj + 1]);
-                        I = 0.0;
-#pragma unroll
-                        for (int q = 0; q < (FK == 2 ? PM_MAX_SOURCES : 1); ++q) Is[q] = 0.0;
-                        n = 0;
-                    } else {  // resume a saved walker where it stopped (an even step count)
-                        const double *S = a.pin.st + tt * DIR_POOL_WORDS;
-                        x.load(S[0], S[1]);
-                        y.load(S[2], S[3]);
-                        I = S[4];
-                        n = (int64_t)S[5];
-                        if constexpr (FK == 2) {
-#pragma unroll
-                            for (int q = 0; q < PM_MAX_SOURCES; ++q) Is[q] = S[6 + q];
-                        }
-                        pi = a.pin.ij[2 * tt];
-                        pj = a.pin.ij[2 * tt + 1];
-                    }
-                    t = (int64_t)pj * a.np + pi;
-                    has = true;
-                } else {
-                    done = true;
-                }
-            }
-        }
-        const unsigned long long hm = __ballot(has);
-        if (hm == 0) break;
-        // compaction: the input is exhausted for this wave and too few lanes
-        // are still walking; hand the walkers to the next launch
-        if (a.dump_below > 0 && iters >= a.min_iters && __ballot(done) != 0 &&
-            __popcll(hm) < a.dump_below) {
-            const int first = __ffsll((long long)hm) - 1;
-            unsigned long long base = 0;
-            if (lane == first) base = atomicAdd(a.pout.count, (unsigned long long)__popcll(hm));
-            base = __shfl(base, first);
-            if (has) {
-                const int64_t slot = (int64_t)base + __popcll(hm & ((1ull << lane) - 1ull));
-                double *S = a.pout.st + slot * DIR_POOL_WORDS;
-                x.save(S[0], S[1]);
-                y.save(S[2], S[3]);
-                S[4] = I;
-                S[5] = (double)n;
-                if constexpr (FK == 2) {
-#pragma unroll
-                    for (int q = 0; q < PM_MAX_SOURCES; ++q) S[6 + q] = Is[q];
-                }
-                a.pout.ij[2 * slot] = pi;
-                a.pout.ij[2 * slot + 1] = pj;
-            }
-            break;
-        }
-        ++iters;
-        const U4 w = philox4x32_10((uint32_t)(n >> 1), pi, pj, 0u, k0, k1);
-        T z0, z1, z2, z3;
-        box_muller(w.x, w.y, z0, z1);
-        box_muller(w.z, w.w, z2, z3);
-        substep(z0, z1);
-        substep(z2, z3);
-    }
+    });
 }
 
 // Payoff of Theorem 3.2, theta_dD(X_tau) - int_0^tau f dt (no boundary term

@@ -11,6 +11,7 @@ namespace pm {
 // 1 <= K <= MX_MAX_K (B = 2K + 1 <= 16 basis functions per axis).
 // ---------------------------------------------------------------------------
 constexpr int MX_MAX_K = 7;
+constexpr int MX_MAX_K_DISK = 4;         // the disk's three forms: 3 x 9 rows of the 32-row tile
 constexpr int MX_BASIS_SHIFT = 8;        // the x basis enters the products scaled by 2^8
 constexpr int64_t MX_SET_BYTES = 2112;   // per parameter set: 64-byte header, A hi, A lo (64 lanes x 16 B)
 
@@ -22,10 +23,11 @@ struct MxHeader {
 static_assert(sizeof(MxHeader) == 64, "operand alignment");
 
 struct MxPackArgs {
-    const double *coef;   // FP64 torus coefficients of k_fold, [n_sets][coef_stride]
+    const double *coef;   // FP64 coefficients of k_fold (torus or disk rows), [n_sets][coef_stride]
     int64_t coef_stride;
     int K;
     int row_stride;
+    int domain;           // PM_TORUS (two forms) or PM_DISK (three)
 };
 
 // Particle coordinates of the small-K kernels are 32-bit fractions of the
@@ -48,7 +50,8 @@ struct MxStepArgs {
     const uint32_t *i;
     const uint32_t *j;
     uint64_t seed;
-    StepConsts<float> fx;  // dt (hi + lo) and sqrt(2 kappa dt), each x 2^32
+    StepConsts<float> fx;  // torus: dt (hi + lo) and sqrt(2 kappa dt), each x 2^32
+    StepConsts<float> sc;  // disk: the same unscaled (double-float coordinates)
     float v0x, v0y;
     double *Y;  // step mode
     double *V;  // velocity mode when non-null (n, i, j, Y unused)
@@ -56,6 +59,8 @@ struct MxStepArgs {
 
 hipError_t launch_pack_mx(const MxPackArgs &a, unsigned char *out, int n_sets, hipStream_t st);
 hipError_t launch_time_mx(const MxTimeArgs &a, int K, int n_cu, int bpc, hipStream_t st);
-hipError_t launch_step_mx(const MxStepArgs &a, int K, hipStream_t st);
+hipError_t launch_step_mx(const MxStepArgs &a, int K, int domain, hipStream_t st);
+hipError_t launch_dirichlet_mx(const DirArgs<float> &a, const unsigned char *set, int K, int fk, int n_cu, int bpc,
+                               hipStream_t st);
 
 }  // namespace pm

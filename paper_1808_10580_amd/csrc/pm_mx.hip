@@ -1,6 +1,7 @@
 // pm_mx.hip -- the velocity field of eq. v_expand on the torus for small
 // wavenumber cutoffs (1 <= K <= 7, B = 2K + 1 <= 15 basis functions per
-// axis), FP32 particles, with the bilinear forms on the matrix cores.
+// axis), FP32 particles, with the bilinear forms on the matrix cores; the same
+// for the disk's three forms (K <= 4) inside the walk of Algorithm 2.
 //
 // With the axis bases phi_0 = 1, phi_{2n-1} = cos 2 pi n s, phi_{2n} =
 // sin 2 pi n s the field is
@@ -30,6 +31,7 @@
 // particle in a fixed order, so the result is identical in every launch
 // shape.
 #include "pm_mx.h"
+#include "pm_walk.h"
 
 namespace pm {
 
@@ -47,10 +49,11 @@ __global__ __launch_bounds__(256) void k_pack_mx(const MxPackArgs a, unsigned ch
     __shared__ double red[256];
     const int B = 2 * a.K + 1;
     const int R = a.row_stride;
+    const int nf = a.domain == PM_DISK ? 3 : 2;  // forms per row: (Psi,) Cx, Cy
     const double *__restrict__ C = a.coef + (int64_t)blockIdx.x * a.coef_stride;
     double m = 0.0;
-    for (int e = threadIdx.x; e < 2 * B * B; e += blockDim.x) {
-        const int j = e / (2 * B), q = e % (2 * B);
+    for (int e = threadIdx.x; e < nf * B * B; e += blockDim.x) {
+        const int j = e / (nf * B), q = e % (nf * B);
         m = fmax(m, fabs(C[j * R + q]));
     }
     red[threadIdx.x] = m;
@@ -80,9 +83,16 @@ __global__ __launch_bounds__(256) void k_pack_mx(const MxPackArgs a, unsigned ch
     for (int t = threadIdx.x; t < 64 * 8; t += blockDim.x) {
         const int lane = t >> 3, e = t & 7;
         const int row = lane & 31, i = 8 * (lane >> 5) + e;
-        const int comp = row >> 4, j = row & 15;
+        int comp, j;
+        if (nf == 2) {  // torus: rows 0..15 Cx, 16..31 Cy
+            comp = row >> 4;
+            j = row & 15;
+        } else {  // disk: rows 8f + j (j < 8) and 24 + f (j = 8) for form f
+            comp = row < 24 ? row >> 3 : (row < 27 ? row - 24 : -1);
+            j = row < 24 ? row & 7 : 8;
+        }
         double v = 0.0;
-        if (i < B && j < B) v = ldexp(C[j * R + 2 * i + comp], sc);
+        if (comp >= 0 && i < B && j < B) v = ldexp(C[j * R + nf * i + comp], sc);
         const _Float16 h = (_Float16)(float)v;
         hi[t] = h;
         lo[t] = (_Float16)(float)(v - (double)(float)h);
@@ -146,14 +156,16 @@ __device__ __forceinline__ void split_pair(float v0, float v1, uint32_t &hi, uin
     lo = l;
 }
 
+// The contraction W = A^T Phi_x for the 64 particles of a wave: x basis x 2^8
+// split into FP16 pairs (P holds entries 0..7, Q 8..15; entries past B are
+// zero), the half-wave swaps that make P the B operand of column block 0
+// (particles 0..31) and Q that of block 1 (32..63), and the three split
+// products per block.
 template <int K>
-__device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, float inv, float xh, float yh,
-                                            float &vx, float &vy)
+__device__ __forceinline__ void mx_contract(const h16x8 ahi, const h16x8 alo, float xh, f32x16 &d0, f32x16 &d1)
 {
     constexpr int B = 2 * K + 1;
     static_assert(K >= 1 && B <= 16, "small-K path");
-    // x basis x 2^8 split into FP16 pairs; P holds entries 0..7, Q 8..15
-    // (entries past B are zero)
     float px[16];
     scaled_basis<K>(xh, px);
     uint32_t Ph[4], Pl[4], Qh[4], Ql[4];
@@ -168,8 +180,6 @@ __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, fl
             (half ? Ql : Pl)[d] = lo;
         }
     }
-    // after the swaps P is the B operand of column block 0 (particles 0..31)
-    // and Q that of column block 1 (particles 32..63)
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         swap_halves(Ph[d], Qh[d]);
@@ -179,13 +189,24 @@ __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, fl
     const h16x8 b0l = __builtin_bit_cast(h16x8, (u32x4){Pl[0], Pl[1], Pl[2], Pl[3]});
     const h16x8 b1h = __builtin_bit_cast(h16x8, (u32x4){Qh[0], Qh[1], Qh[2], Qh[3]});
     const h16x8 b1l = __builtin_bit_cast(h16x8, (u32x4){Ql[0], Ql[1], Ql[2], Ql[3]});
-    f32x16 d0 = {}, d1 = {};
+    d0 = f32x16{};
+    d1 = f32x16{};
     d0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, b0h, d0, 0, 0, 0);
     d1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, b1h, d1, 0, 0, 0);
     d0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, b0l, d0, 0, 0, 0);
     d1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahi, b1l, d1, 0, 0, 0);
     d0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, b0h, d0, 0, 0, 0);
     d1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, b1h, d1, 0, 0, 0);
+}
+
+// Torus: rows q < 16 are Cx[.][j = q], rows q >= 16 Cy[.][j = q - 16].
+template <int K>
+__device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, float inv, float xh, float yh,
+                                            float &vx, float &vy)
+{
+    constexpr int B = 2 * K + 1;
+    f32x16 d0, d1;
+    mx_contract<K>(ahi, alo, xh, d0, d1);
 
     // y basis (FP32, unscaled) while the matrix cores work: Py = entries
     // {0..3, 8..11}, Qy = {4..7, 12..15}; after the swaps Py serves column
@@ -218,6 +239,63 @@ __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, fl
     swap_halves(ay0, ay1);
     vx = (ax0 + ax1) * inv;
     vy = (ay0 + ay1) * inv;
+}
+
+// Disk, psi = chi psi_F with chi = (1 - r^2)^2 (K <= 4, B <= 9): rows 8f + j
+// hold form f (0: Psi, 1: Cx, 2: Cy) at j = 0..7 and rows 24 + f the forms
+// at j = 8.  A lane's D registers r = 0..3, 4..7 and 8..11 are the three
+// forms at j = 4h + (r mod 4), and r = 12, 13, 14 the j = 8 rows (lower
+// half-wave; the upper half's rows 28..31 are zero rows), so five y-basis
+// values per particle, {phi_0..3, phi_8} or {phi_4..7, 0}, serve all three
+// forms.  Then v = grad-perp (chi psi_F) by the product rule, as the vector
+// engine forms it.
+template <int K>
+__device__ __forceinline__ void mx_velocity_disk(const h16x8 ahi, const h16x8 alo, float inv, float xh, float yh,
+                                                 float &vx, float &vy)
+{
+    constexpr int B = 2 * K + 1;
+    static_assert(K >= 1 && B <= 9, "disk rows");
+    f32x16 d0, d1;
+    mx_contract<K>(ahi, alo, xh, d0, d1);
+    float py[16];
+    trig_basis<float, K>(yh, py);
+#pragma unroll
+    for (int e = B; e < 16; ++e) py[e] = 0.f;
+    float Py[5], Qy[5];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        Py[q] = py[q];
+        Qy[q] = py[4 + q];
+    }
+    Py[4] = py[8];
+    Qy[4] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) swap_halves(Py[q], Qy[q]);
+    float f0[2], fx[2], fy[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const f32x16 &D = b ? d1 : d0;
+        const float *Y = b ? Qy : Py;
+        float s0 = D[12] * Y[4], sx = D[13] * Y[4], sy = D[14] * Y[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            s0 = __builtin_fmaf(D[r], Y[r], s0);
+            sx = __builtin_fmaf(D[4 + r], Y[r], sx);
+            sy = __builtin_fmaf(D[8 + r], Y[r], sy);
+        }
+        f0[b] = s0;
+        fx[b] = sx;
+        fy[b] = sy;
+    }
+    swap_halves(f0[0], f0[1]);
+    swap_halves(fx[0], fx[1]);
+    swap_halves(fy[0], fy[1]);
+    const float F0 = (f0[0] + f0[1]) * inv, FX = (fx[0] + fx[1]) * inv, FY = (fy[0] + fy[1]) * inv;
+    const float w = 1.f - (xh * xh + yh * yh);
+    const float chi = w * w;
+    const float g4 = 4.f * w * F0;
+    vx = __builtin_fmaf(chi, FX, -(g4 * yh));
+    vy = __builtin_fmaf(chi, FY, g4 * xh);
 }
 
 // ---------------------------------------------------------------------------
@@ -389,6 +467,52 @@ __global__ __launch_bounds__(256) void k_step_mx(const MxStepArgs a)
     a.Y[2 * e + 1] = ny;
 }
 
+// Algorithm 2 on the disk with the matrix-core velocity (the walk, refills,
+// exits and compaction of the vector kernel).
+template <int K, int FK>
+__global__ __launch_bounds__(256) void k_dirichlet_mx(const DirArgs<float> a, const unsigned char *set)
+{
+    const int lane = threadIdx.x & 63;
+    h16x8 ahi, alo;
+    float inv;
+    load_set(set, lane, ahi, alo, inv);
+    dirichlet_walk<float, FK, PM_DISK>(
+        a, [&](float xa, float ya, float &vx, float &vy) { mx_velocity_disk<K>(ahi, alo, inv, xa, ya, vx, vy); });
+}
+
+// Teacher-forced steps and velocity on the disk (double-float coordinates,
+// no wrap).
+template <int K>
+__global__ __launch_bounds__(256) void k_step_mx_disk(const MxStepArgs a)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool act = e < a.count;
+    h16x8 ahi, alo;
+    float inv;
+    load_set(a.set, lane, ahi, alo, inv);
+    Coord<float> x, y;
+    x.set(act ? a.X[2 * e] : 0.0);
+    y.set(act ? a.X[2 * e + 1] : 0.0);
+    float vx, vy;
+    mx_velocity_disk<K>(ahi, alo, inv, x.at(), y.at(), vx, vy);
+    if (!act) return;
+    if (a.V) {
+        a.V[2 * e] = (double)(vx + a.v0x);
+        a.V[2 * e + 1] = (double)(vy + a.v0y);
+        return;
+    }
+    const uint64_t n = a.n[e];
+    const U4 w = philox4x32_10((uint32_t)(n >> 1), a.i[e], a.j[e], 0u, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+    float z0, z1;
+    if ((n & 1) == 0) box_muller(w.x, w.y, z0, z1);
+    else box_muller(w.z, w.w, z0, z1);
+    x.advance(vx + a.v0x, z0, a.sc);
+    y.advance(vy + a.v0y, z1, a.sc);
+    a.Y[2 * e] = x.value();
+    a.Y[2 * e + 1] = y.value();
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
@@ -440,13 +564,47 @@ hipError_t launch_time_mx(const MxTimeArgs &a, int K, int n_cu, int bpc, hipStre
     });
 }
 
-hipError_t launch_step_mx(const MxStepArgs &a, int K, hipStream_t st)
+hipError_t launch_step_mx(const MxStepArgs &a, int K, int domain, hipStream_t st)
 {
+    if (domain == PM_DISK && K > MX_MAX_K_DISK) return hipErrorInvalidValue;
     return dispatch_mx(K, [&](auto kc) -> hipError_t {
         constexpr int KK = decltype(kc)::value;
         const int64_t blocks = (a.count + 255) / 256;
+        if constexpr (KK <= MX_MAX_K_DISK) {
+            if (domain == PM_DISK) {
+                hipLaunchKernelGGL(k_step_mx_disk<KK>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+                return hipGetLastError();
+            }
+        }
         hipLaunchKernelGGL(k_step_mx<KK>, dim3((unsigned)blocks), dim3(256), 0, st, a);
         return hipGetLastError();
+    });
+}
+
+hipError_t launch_dirichlet_mx(const DirArgs<float> &a, const unsigned char *set, int K, int fk, int n_cu, int bpc,
+                               hipStream_t st)
+{
+    if (K < 1 || K > MX_MAX_K_DISK || (fk != 0 && fk != 1)) return hipErrorInvalidValue;
+    return dispatch_mx(K, [&](auto kc) -> hipError_t {
+        constexpr int KK = decltype(kc)::value;
+        if constexpr (KK > MX_MAX_K_DISK) {
+            return hipErrorInvalidValue;
+        } else {
+            void (*kern)(const DirArgs<float>, const unsigned char *) =
+                fk == 0 ? k_dirichlet_mx<KK, 0> : k_dirichlet_mx<KK, 1>;
+            int per_cu = 0;
+            hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
+            if (err != hipSuccess) return err;
+            if (per_cu < 1) per_cu = 1;
+            if (per_cu > 8) per_cu = 8;  // the compaction pools hold dirichlet_max_lanes() walkers
+            if (bpc > 0 && bpc < per_cu) per_cu = bpc;
+            int64_t blocks = (int64_t)per_cu * n_cu;
+            const int64_t need = (a.total + 255) / 256;
+            if (blocks > need) blocks = need;
+            if (blocks < 1) blocks = 1;
+            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, st, a, set);
+            return hipGetLastError();
+        }
     });
 }
 

@@ -57,7 +57,7 @@ def run(n_train=8192, train_particles=10_000, iters=2000, pilot=60, chain_partic
     std = W.prior_std(wl.modes)
     prior_std = np.concatenate([std, std])
     ctx = pm.Context(0)
-    ctx.set_time_engine(engine)
+    ctx.set_velocity_engine(engine)
     prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
     if engine == "valu":
         prob.autotune_time(wl.u, wl.obs, wl.kappa, wl.dt, chain_particles, wl.seed, n_probe_steps=50)

@@ -41,10 +41,10 @@ def np_(t):
 @pytest.fixture
 def engine_of(ctx):
     def use(name):
-        ctx.set_time_engine(name)
+        ctx.set_velocity_engine(name)
         return name
     yield use
-    ctx.set_time_engine("auto")
+    ctx.set_velocity_engine("auto")
 
 
 @pytest.mark.parametrize("engine", ["valu", "mfma"])

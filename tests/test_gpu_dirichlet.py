@@ -11,6 +11,8 @@
     the observation means agree with the oracle's by a paired 4-SE test;
   - capped paths are counted and reported by pm_sync;
   - the full-size disk workload against an oracle subsample.
+FP32 disk checks run for both velocity engines: the vector FMAs ("valu") and
+the matrix-core contraction of the three forms ("mfma", the default for K <= 4).
 """
 import math
 
@@ -45,13 +47,25 @@ def np_(t):
     return t.detach().cpu().numpy()
 
 
+@pytest.fixture
+def engine_of(ctx):
+    """Select a velocity engine for one test; the default is restored after."""
+    def use(name):
+        ctx.set_velocity_engine(name)
+        return name
+    yield use
+    ctx.set_velocity_engine("auto")
+
+
 def _flow(scale=1.0):
     wl = W.dirichlet_main()
     return wl.modes, wl.u * scale
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-6)])
-def test_teacher_forced_disk_steps(pm, ctx, orc, prec, tol):
+@pytest.mark.parametrize("prec,tol,engine", [("fp64", 1e-13, "auto"), ("fp32", 1e-6, "valu"),
+                                            ("fp32", 1e-6, "mfma")])
+def test_teacher_forced_disk_steps(pm, ctx, orc, engine_of, prec, tol, engine):
+    engine_of(engine)
     modes, u = _flow()
     kappa, dt = 0.02, 1e-4
     rows = []
@@ -111,7 +125,9 @@ def test_fp64_dirichlet_full_strength_flow(pm, ctx, orc):
     assert np.all(z < 4.5), z
 
 
-def test_fp32_dirichlet_paths_and_means(pm, ctx, orc):
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+def test_fp32_dirichlet_paths_and_means(pm, ctx, orc, engine_of, engine):
+    engine_of(engine)
     # weak flow: FP32 paths follow the oracle's; an exit step differs only when
     # the path passes within FP32 rounding of the circle
     out, st, ref = _run_both(pm, ctx, orc, "fp32", Np=1000, scale=0.1)
@@ -120,8 +136,8 @@ def test_fp32_dirichlet_paths_and_means(pm, ctx, orc):
     same = P[..., 3].astype(np.int64) == ref["tau_steps"]
     frac = 1 - same.mean()
     err = np.max(np.abs(P[..., :2][same] - ref["exit"][same]), axis=-1)
-    print("fp32 Dirichlet, weak flow: different exit steps %.4f; exit point error p99 %.2e max %.2e"
-          % (frac, np.quantile(err, 0.99), err.max()))
+    print("fp32 Dirichlet %s, weak flow: different exit steps %.4f; exit point error p99 %.2e max %.2e"
+          % (engine, frac, np.quantile(err, 0.99), err.max()))
     assert frac <= 0.01
     assert np.quantile(err, 0.99) <= 1e-5
     # full-strength flow: paired mean test on the same Philox streams
@@ -155,9 +171,11 @@ def test_capped_paths_reported(pm, ctx, orc):
     assert ctx.sync() == pm.PM_OK  # flags are cleared
 
 
-def test_full_size_disk_workload_against_oracle_subsample(pm, ctx, orc):
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+def test_full_size_disk_workload_against_oracle_subsample(pm, ctx, orc, engine_of, engine):
     """Disk workload at full size (25 x 5e4 particles, dt = 1e-4, walk to exit);
     the oracle walks the first 24 particles of every point."""
+    engine_of(engine)
     wl = W.dirichlet_main()
     prob = pm.Problem(ctx, "disk", wl.modes, prec="fp32")
     out = prob.observe_dirichlet(wl.u, wl.f, wl.g, wl.obs, wl.kappa, wl.dt, wl.n_particles, wl.seed,
@@ -173,7 +191,8 @@ def test_full_size_disk_workload_against_oracle_subsample(pm, ctx, orc):
     assert np.sum(zt > 3) <= 2 and np.all(zt < 4.5), zt
 
 
-def test_coefficient_sources_are_bitwise_identical(pm, ctx):
+def test_coefficient_sources_are_bitwise_identical(pm, ctx, engine_of):
+    engine_of("valu")  # the coefficient source is a knob of the vector kernel
     modes, u = _flow()
     prob = pm.Problem(ctx, "disk", modes, prec="fp32")
     res = []
@@ -187,11 +206,12 @@ def test_coefficient_sources_are_bitwise_identical(pm, ctx):
     assert np.array_equal(res[0], res[1])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec,engine", [("fp32", "valu"), ("fp32", "mfma"), ("fp64", "auto")])
 @pytest.mark.parametrize("dump,launches", [(32, 8), (64, 3), (8, 20)])
-def test_compaction_is_bitwise_neutral(pm, ctx, prec, dump, launches):
+def test_compaction_is_bitwise_neutral(pm, ctx, engine_of, prec, engine, dump, launches):
     """Saving tail walkers between launches and resuming them elsewhere changes
     nothing: every path, payoff, exit step and statistic is identical."""
+    engine_of(engine)
     wl = W.dirichlet_main(n_particles=2000, prec=prec)
     prob = pm.Problem(ctx, "disk", wl.modes, prec=prec)
     res = []

@@ -53,7 +53,7 @@ def test_fp64_jacobian_matches_oracle(pm, ctx, orc):
 
 @pytest.mark.parametrize("modes_name,engine", [("k6", "valu"), ("k6", "mfma"), ("k9", "auto")])
 def test_columns_equal_separate_calls_bitwise(pm, ctx, modes_name, engine):
-    ctx.set_time_engine(engine)
+    ctx.set_velocity_engine(engine)
     wl = W.time_main()
     modes = wl.modes if modes_name == "k6" else W.torus_modes(9)
     u = wl.u if modes_name == "k6" else W.draw_prior(modes, np.random.default_rng(2))
@@ -69,7 +69,7 @@ def test_columns_equal_separate_calls_bitwise(pm, ctx, modes_name, engine):
         col = (np_(mp) - np_(mm)) / (up[k] - um[k])
         assert np.array_equal(J[:, k], col), (modes_name, k)
     prob.close()
-    ctx.set_time_engine("auto")
+    ctx.set_velocity_engine("auto")
 
 
 def test_invalid_step_raises(pm, ctx):

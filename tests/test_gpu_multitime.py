@@ -57,7 +57,7 @@ def test_fp64_matches_oracle(pm, ctx, orc, steps, Np):
 
 @pytest.mark.parametrize("prec,engine", [("fp64", "auto"), ("fp32", "valu"), ("fp32", "mfma")])
 def test_each_readout_equals_a_single_time_call(pm, ctx, prec, engine):
-    ctx.set_time_engine(engine)
+    ctx.set_velocity_engine(engine)
     wl = W.time_main()
     steps = [0, 1, 50, 123, 300]
     Np = 700
@@ -69,12 +69,12 @@ def test_each_readout_equals_a_single_time_call(pm, ctx, prec, engine):
         m1, v1 = prob.observe_time(wl.u, wl.obs, wl.kappa, n * DT, DT, Np, wl.seed)
         assert np.array_equal(np_(m[k]), np_(m1)) and np.array_equal(np_(v[k]), np_(v1)), (prec, n)
     prob.close()
-    ctx.set_time_engine("auto")
+    ctx.set_velocity_engine("auto")
 
 
 @pytest.mark.parametrize("engine", ["valu", "mfma"])
 def test_fp32_means_main_workload(pm, ctx, orc, engine):
-    ctx.set_time_engine(engine)
+    ctx.set_velocity_engine(engine)
     wl = W.time_main()
     steps = [250, 500, 1000]
     Np = 512
@@ -85,7 +85,7 @@ def test_fp32_means_main_workload(pm, ctx, orc, engine):
     se = np.sqrt((np_(v) + vr) / Np) + 1e-300
     z = np.abs(np_(m) - mr) / se
     print("multi-time fp32 %s: max z %.2f" % (engine, z.max()))
-    ctx.set_time_engine("auto")
+    ctx.set_velocity_engine("auto")
     assert np.sum(z > 3) <= 3 and np.all(z < 4.5), z
     prob.close()
 
