@@ -63,8 +63,8 @@ __device__ __forceinline__ void dirichlet_walk(const DirArgs<T> &a, Vel &&veloci
         nx.advance(vx + a.v0x, z0, a.sc);
         ny.advance(vy + a.v0y, z1, a.sc);
         if (has) {
-            const double xd = x.value(), yd = y.value();
             if constexpr (FK == 2) {  // left point, one integral per Gaussian source
+                const double xd = x.value(), yd = y.value();
 #pragma unroll
                 for (int q = 0; q < PM_MAX_SOURCES; ++q) {
                     if (q < a.n_src) {
@@ -73,13 +73,27 @@ __device__ __forceinline__ void dirichlet_walk(const DirArgs<T> &a, Vel &&veloci
                     }
                 }
             } else {
-                I += source_at<FK>(a.f, xd, yd) * a.dtd;  // left point
+                I += source_at<FK>(a.f, x.value(), y.value()) * a.dtd;  // left point
             }
             n += 1;
-            const double nxd = nx.value(), nyd = ny.value();
-            bool out;
-            if constexpr (DOM == PM_DISK) out = nxd * nxd + nyd * nyd >= 1.0;
-            else out = !(nxd > 0.0 && nxd < 1.0 && nyd > 0.0 && nyd < 1.0);
+            // The exit test is decided in FP64.  FP32 particles first try the
+            // high words: inside by more than 2^-18 (far above the 2^-21 that
+            // the low words and FP32 rounding can move the test), the FP64
+            // test would say inside too, so it is skipped.
+            bool check = true;
+            if constexpr (std::is_same<T, float>::value) {
+                constexpr float m = 0x1p-18f;
+                if constexpr (DOM == PM_DISK) check = !(__builtin_fmaf(nx.hi, nx.hi, ny.hi * ny.hi) < 1.f - m);
+                else check = !(nx.hi > m && nx.hi < 1.f - m && ny.hi > m && ny.hi < 1.f - m);
+            }
+            bool out = false;
+            double nxd = 0.0, nyd = 0.0;
+            if (check) {
+                nxd = nx.value();
+                nyd = ny.value();
+                if constexpr (DOM == PM_DISK) out = nxd * nxd + nyd * nyd >= 1.0;
+                else out = !(nxd > 0.0 && nxd < 1.0 && nyd > 0.0 && nyd < 1.0);
+            }
             if (out) {
                 // exit point: the nearest boundary point (radial projection
                 // onto the circle; clamping onto the square)
@@ -90,7 +104,7 @@ __device__ __forceinline__ void dirichlet_walk(const DirArgs<T> &a, Vel &&veloci
                     finish(fmin(fmax(nxd, 0.0), 1.0), fmin(fmax(nyd, 0.0), 1.0), true);
                 }
             } else if (n >= a.max_steps) {
-                finish(nxd, nyd, false);
+                finish(nx.value(), ny.value(), false);
             } else {
                 x = nx;
                 y = ny;
