@@ -38,16 +38,17 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 # reported when the sources still hash to the recorded value, else null.
 # Per velocity engine: (bytes per launch, SHA-256 of the kernel's sources).
 COUNTER_TRAFFIC = {
-    # k_time<float,6,3>: FETCH 164.44 KiB x 2 + WRITE 77,480.78 KiB x 1
-    "valu": (79_677_088, "8b10e57c6dce9afde4afa80eca8b44c376325c8b25fd1cc6dd045b05e78faab5"),
-    # k_time_mx<6>: FETCH 66.56 KiB x 2 + WRITE 79,172.34 KiB x 1
-    "mfma": (81_208_800, "bc2b7d0f968032e7516bfffcf59b964655b11843a9119db6a2d406ea4a04bd95"),
+    # k_time<float,6,3>: FETCH 164.50 KiB x 2 + WRITE 77,480.78 KiB x 1
+    "valu": (79_677_216, "fb42326f53cd55ae5fe7e78b87d1b5a828335e4ab4d5dd6d85cfd2fc29352d35"),
+    # k_time_mx<6>: FETCH 68.38 KiB x 2 + WRITE 79,172.34 KiB x 1
+    "mfma": (81_212_512, "19b7d79a2d25330cb31ec25c49032f38a3bc7665619096c340428eeefd690b1f"),
 }
 KERNEL_SOURCES = {
     "valu": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
-             "paper_1808_10580_amd/csrc/pm_kernels.hip"),
+             "paper_1808_10580_amd/csrc/pm_walk.h", "paper_1808_10580_amd/csrc/pm_kernels.hip"),
     "mfma": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
-             "paper_1808_10580_amd/csrc/pm_mx.h", "paper_1808_10580_amd/csrc/pm_mx.hip"),
+             "paper_1808_10580_amd/csrc/pm_walk.h", "paper_1808_10580_amd/csrc/pm_mx.h",
+             "paper_1808_10580_amd/csrc/pm_mx.hip"),
 }
 # Matrix-core FLOPs issued per particle-step by the small-K engine: per 64
 # particles two 32-column blocks x three v_mfma_f32_32x32x16_f16 (32 x 32 x 16
