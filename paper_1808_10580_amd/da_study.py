@@ -124,10 +124,16 @@ def run(n_train=8192, train_particles=10_000, iters=2000, pilot=60, chain_partic
                              surrogate=surf if kind != "plain" else None, gamma_s=gamma_s)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if kind == "plain":
-            mcmc.pcn_steps(c, iters, fwd, prior_std, y, gamma, beta)
-        else:
-            mcmc.da_pcn_steps(c, iters, fwd, surf, prior_std, y, gamma, beta, gamma_s=gamma_s)
+        done = 0
+        while done < iters:  # blocks of 500 iterations with a progress line
+            nb = min(500, iters - done)
+            if kind == "plain":
+                mcmc.pcn_steps(c, nb, fwd, prior_std, y, gamma, beta)
+            else:
+                mcmc.da_pcn_steps(c, nb, fwd, surf, prior_std, y, gamma, beta, gamma_s=gamma_s)
+            done += nb
+            if verbose:
+                print(f"[da] {kind}: {done}/{iters} iterations, {time.perf_counter() - t0:.1f} s", flush=True)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         S = np.array(c.samples)
