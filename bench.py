@@ -165,6 +165,53 @@ def _time_steps(run, steps, warmup, ctx):
     return time.perf_counter() - t0, kernel_ms, work
 
 
+def bench_modes_sweep(args):
+    """Cost of the forward map against the number of modes N_u (the paper's
+    cost model is linear in N_u): Euclidean balls |k|_2 <= R of the turbulent
+    workload's problem (2 points x 1e5 particles, kappa 3e-5, dt = 1/9600),
+    960 steps each, the fastest of three maps per R.  Prints one JSON line with
+    a row per R (and the vector engine beside the default for K <= 8)."""
+    import numpy as np
+    import torch
+    import paper_1808_10580_amd as pm
+    import workloads as W
+
+    wl = W.turbulent_k80()
+    ctx = pm.Context(0)
+    obs = torch.tensor(wl.obs, dtype=torch.float64, device="cuda")
+    nst = 960
+    rows = []
+    for R in (4, 6, 8, 12, 16, 24, 32, 40, 48, 64, 80):
+        full = W.l2_ball_modes(float(R))
+        modes = W.half_plane(full)
+        u = torch.tensor(W.draw_prior(modes, np.random.default_rng([W.WORKLOAD_SEED, R])), dtype=torch.float64,
+                         device="cuda")
+        prob = pm.Problem(ctx, "torus", modes, theta0=wl.theta0, prec="fp32")
+        K = int(np.abs(modes).max())
+        for eng in (("auto", "valu") if K <= pm.MAX_K else ("auto",)):
+            ctx.set_velocity_engine(eng)
+            ms = []
+            for _ in range(3):
+                prob.observe_time(u, obs, wl.kappa, nst * wl.dt, wl.dt, wl.n_particles, wl.seed)
+                st = ctx.sync()
+                if st != pm.PM_OK:
+                    raise pm.PMError(st, "forward map")
+                ms.append(ctx.last_kernel_stats()[0])
+            steps = 2 * wl.n_particles * nst
+            path = ("matrix cores, small K" if engine_in_use(pm, eng, K) == "mfma"
+                    else ("vector units" if K <= pm.MAX_K else "matrix cores, high K"))
+            rows.append({"R": R, "K": K, "N_u": int(len(full)), "path": path, "kernel_ms": round(min(ms), 3),
+                         "ns_per_particle_step": round(min(ms) * 1e6 / steps, 4)})
+            print(f"[bench] R={R} N_u={len(full)} {path}: {min(ms):.3f} ms", file=sys.stderr, flush=True)
+        ctx.set_velocity_engine("auto")
+        prob.close()
+    print(json.dumps({"metric": "forward-map time per particle-step against N_u", "unit": "ns",
+                      "data": "synthetic", "config": {"workload": "torus-modes-sweep: |k|_2 <= R, 2 points x 1e5 "
+                                                                  "particles, 960 steps, kappa 3e-5"},
+                      "rows": rows}))
+    ctx.close()
+
+
 def bench_other(args):
     """Secondary workloads (not the default line): the turbulent |k|_2 <= 80
     problem on the matrix cores, the Dirichlet walk on the disk, and the
@@ -291,13 +338,17 @@ def main():
     ap.add_argument("--engine", default="auto", choices=["auto", "valu", "mfma"],
                     help="velocity engine of the FP32 torus time kernel (auto = matrix cores for K <= 7)")
     ap.add_argument("--workload", default="torus-k6-fp32",
-                    help="torus-k6-fp32 (the benchmark line), torus-k80-turbulent, disk-dirichlet, torus-k6-batch")
+                    help="torus-k6-fp32 (the benchmark line), torus-k80-turbulent, disk-dirichlet, torus-k6-batch, "
+                         "torus-modes-sweep")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the particle map's "
               "multi-GPU sharding is described in DESIGN.md and not built.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "torus-modes-sweep":
+        bench_modes_sweep(args)
+        return
     if args.workload != "torus-k6-fp32":
         bench_other(args)
         return
