@@ -373,6 +373,48 @@ def test_ragged_particle_counts_fp64(pm, ctx, orc, Np):
         assert np.all(np_(v) == 0)
 
 
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+@pytest.mark.parametrize("Np", [1, 63, 64, 65, 129])
+def test_ragged_particle_counts_fp32(pm, ctx, orc, engine_of, engine, Np):
+    """Ragged chunks and one particle on both FP32 engines: 13 steps (odd) of
+    the small workload, endpoints within the FP32 path contract and the GPU's
+    means equal to the mean of its own endpoints' payoffs."""
+    engine_of(engine)
+    wl = W.time_small()
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+    T = 0.013
+    m, v, ep = prob.observe_time(wl.u, wl.obs, wl.kappa, T, wl.dt, Np, 9, endpoints=True)
+    _, ep_ref = orc.observe_time_payoffs(wl.modes, wl.u, wl.theta0, wl.obs, wl.kappa, T, wl.dt, Np, 9,
+                                         endpoints=True)
+    assert ep.shape[1] == Np
+    assert np.max(tdist(np_(ep), ep_ref)) <= 1e-6
+    e_gpu = theta0_numpy(wl.theta0, np_(ep))
+    assert np.allclose(np_(m), e_gpu.mean(axis=1), rtol=0, atol=1e-12)
+    if Np == 1:
+        assert np.all(np_(v) == 0)
+
+
+def test_teacher_forced_steps_largest_small_k(pm, ctx, orc, engine_of):
+    """K = 7, the largest cutoff of the small-K matrix-core path (B = 15 of
+    16 tile entries), in teacher-forced steps against the oracle."""
+    engine_of("mfma")
+    K = 7
+    modes = W.torus_modes(K)
+    rng = np.random.default_rng(77)
+    u = W.draw_prior(modes, rng)
+    kappa, dt, seed = 0.01, 1e-3, 5
+    X = rng.random((700, 2))
+    n = rng.integers(0, 1000, 700)
+    i = rng.integers(0, 10**5, 700)
+    j = rng.integers(0, 49, 700)
+    prob = pm.Problem(ctx, "torus", modes, theta0=W.fld("zero"), prec="fp32")
+    Y = np_(prob.step(u, X, n, i, j, kappa, dt, seed))
+    Yr = orc.step("torus", modes, u, kappa, dt, seed, X, n, i, j)
+    d = tdist(Y, Yr)
+    print("teacher-forced K=7 mfma: max %.2e" % d.max())
+    assert np.max(d) <= 1e-6
+
+
 def test_empty_mode_table_is_pure_diffusion(pm, ctx, orc):
     prob = pm.Problem(ctx, "torus", np.zeros((0, 2), np.int32), theta0=W.fld("sinsin", [1.0]), prec="fp64")
     obs = np.array([[0.1, 0.3], [0.7, 0.2]])
