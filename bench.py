@@ -336,7 +336,7 @@ def main():
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "kernel that calibrates the profiler's FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--engine", default="auto", choices=["auto", "valu", "mfma"],
-                    help="velocity engine of the FP32 torus time kernel (auto = matrix cores for K <= 7)")
+                    help="velocity engine of FP32 problems (auto = matrix cores for torus K <= 8, disk K <= 4)")
     ap.add_argument("--workload", default="torus-k6-fp32",
                     help="torus-k6-fp32 (the benchmark line), torus-k80-turbulent, disk-dirichlet, torus-k6-batch, "
                          "torus-modes-sweep")

@@ -101,11 +101,12 @@ typedef struct {
  * three products, FP32 accumulation; about FP32 accuracy).  This is the
  * regime of Section 4's turbulent example, |k|_2 <= 80 (20,081 modes). */
 #define PM_MAX_K_MFMA 95
-/* FP32 torus problems with 1 <= K <= PM_MAX_K_MX (B = 2K + 1 <= 15 basis
- * functions per axis) and FP32 disk problems with 1 <= K <= PM_MAX_K_DISK_MX
+/* FP32 torus problems with 1 <= K <= PM_MAX_K_MX (basis entries 0..15 of each
+ * axis on the matrix cores, the entry-16 terms of K = 8 on the vector units)
+ * and FP32 disk problems with 1 <= K <= PM_MAX_K_DISK_MX
  * run the same bilinear forms on the matrix cores by default (engine
  * PM_ENGINE_AUTO; see pm_set_velocity_engine). */
-#define PM_MAX_K_MX 7
+#define PM_MAX_K_MX 8
 #define PM_MAX_K_DISK_MX 4
 
 /* Velocity engines of FP32 problems (pm_set_velocity_engine). */

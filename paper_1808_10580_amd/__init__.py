@@ -28,7 +28,7 @@ FIELD_KINDS = {"zero": 0, "const": 1, "sinsin": 2, "fourier": 3, "gauss_periodic
                "cos_m_theta": 5, "exp_linear": 6, "linear": 7, "gauss": 8, "cos_axes": 9}
 MAX_SOURCES = 4
 MAX_K = 8
-MAX_K_MX = 7  # FP32 torus problems with 1 <= K <= MAX_K_MX use the matrix cores by default
+MAX_K_MX = 8  # FP32 torus problems with 1 <= K <= MAX_K_MX use the matrix cores by default
 MAX_K_DISK_MX = 4  # the same for FP32 disk problems
 ENGINES = {"auto": 0, "valu": 1, "mfma": 2}
 
@@ -194,7 +194,7 @@ class Context:
 
     def set_velocity_engine(self, engine="auto"):
         """Velocity engine of FP32 problems: "auto"/"mfma" (matrix cores for
-        torus 1 <= K <= 7 and disk 1 <= K <= 4) or "valu" (vector FMAs; the
+        torus 1 <= K <= 8 and disk 1 <= K <= 4) or "valu" (vector FMAs; the
         kernel that set_tuning and autotune_time tune)."""
         code = ENGINES[engine] if isinstance(engine, str) else int(engine)
         _check(_lib().pm_set_velocity_engine(self.h, code), "pm_set_velocity_engine")

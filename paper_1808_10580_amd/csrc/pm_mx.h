@@ -8,12 +8,20 @@ namespace pm {
 
 // ---------------------------------------------------------------------------
 // Small-K torus path (pm_mx.hip): split-FP16 matrix-core velocity for
-// 1 <= K <= MX_MAX_K (B = 2K + 1 <= 16 basis functions per axis).
+// 1 <= K <= MX_MAX_K.  Basis entries 0..15 of each axis go through the
+// 16-entry tile; at K = 8 (B = 17) the entry-16 row and column of the
+// coefficient matrices are added on the vector units.
 // ---------------------------------------------------------------------------
-constexpr int MX_MAX_K = 7;
+constexpr int MX_MAX_K = 8;
 constexpr int MX_MAX_K_DISK = 4;         // the disk's three forms: 3 x 9 rows of the 32-row tile
 constexpr int MX_BASIS_SHIFT = 8;        // the x basis enters the products scaled by 2^8
-constexpr int64_t MX_SET_BYTES = 2112;   // per parameter set: 64-byte header, A hi, A lo (64 lanes x 16 B)
+// Per parameter set: 64-byte header, A hi, A lo (64 lanes x 16 B each), then
+// MX_BORDER_FLOATS border coefficients (K = 8): C_c[16][j] for c = x, y and
+// j = 0..16, then C_c[i][16] x 2^-MX_BASIS_SHIFT for i = 0..15.
+constexpr int MX_BORDER_FLOATS = 2 * 17 + 2 * 16;
+constexpr int64_t MX_BORDER_OFFSET = 2112;
+constexpr int64_t MX_SET_BYTES = MX_BORDER_OFFSET + 4 * (MX_BORDER_FLOATS + 2);
+static_assert(MX_SET_BYTES % 16 == 0, "set alignment");
 
 struct MxHeader {
     float inv_scale;  // 2^-(coefficient shift + MX_BASIS_SHIFT)

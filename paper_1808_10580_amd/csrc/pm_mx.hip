@@ -97,6 +97,22 @@ __global__ __launch_bounds__(256) void k_pack_mx(const MxPackArgs a, unsigned ch
         hi[t] = h;
         lo[t] = (_Float16)(float)(v - (double)(float)h);
     }
+    // K = 8 (torus): the entry-16 row and column, FP32, unscaled (the column
+    // carries 2^-8 against the x basis' scale); zeros otherwise
+    float *border = reinterpret_cast<float *>(set + MX_BORDER_OFFSET);
+    for (int t = threadIdx.x; t < MX_BORDER_FLOATS + 2; t += blockDim.x) {
+        float v = 0.f;
+        if (nf == 2 && B == 17 && t < MX_BORDER_FLOATS) {
+            if (t < 34) {
+                const int c = t / 17, j = t % 17;  // C_c[16][j]
+                v = (float)C[j * R + 2 * 16 + c];
+            } else {
+                const int c = (t - 34) / 16, i = (t - 34) % 16;  // C_c[i][16]
+                v = (float)ldexp(C[16 * R + 2 * i + c], -MX_BASIS_SHIFT);
+            }
+        }
+        border[t] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -157,17 +173,16 @@ __device__ __forceinline__ void split_pair(float v0, float v1, uint32_t &hi, uin
 }
 
 // The contraction W = A^T Phi_x for the 64 particles of a wave: x basis x 2^8
-// split into FP16 pairs (P holds entries 0..7, Q 8..15; entries past B are
-// zero), the half-wave swaps that make P the B operand of column block 0
+// (px, from scaled_basis) split into FP16 pairs (P holds entries 0..7, Q
+// 8..15; entries past B are zero), the half-wave swaps that make P the B operand of column block 0
 // (particles 0..31) and Q that of block 1 (32..63), and the three split
 // products per block.
 template <int K>
-__device__ __forceinline__ void mx_contract(const h16x8 ahi, const h16x8 alo, float xh, f32x16 &d0, f32x16 &d1)
+__device__ __forceinline__ void mx_contract(const h16x8 ahi, const h16x8 alo, const float *px, f32x16 &d0,
+                                            f32x16 &d1)
 {
-    constexpr int B = 2 * K + 1;
-    static_assert(K >= 1 && B <= 16, "small-K path");
-    float px[16];
-    scaled_basis<K>(xh, px);
+    constexpr int B = 2 * K + 1 < 16 ? 2 * K + 1 : 16;  // entries in the tile
+    static_assert(K >= 1 && K <= MX_MAX_K, "small-K path");
     uint32_t Ph[4], Pl[4], Qh[4], Ql[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
@@ -199,23 +214,30 @@ __device__ __forceinline__ void mx_contract(const h16x8 ahi, const h16x8 alo, fl
     d1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, b1h, d1, 0, 0, 0);
 }
 
-// Torus: rows q < 16 are Cx[.][j = q], rows q >= 16 Cy[.][j = q - 16].
+// Torus: rows q < 16 are Cx[.][j = q], rows q >= 16 Cy[.][j = q - 16].  At
+// K = 8 the tile holds i, j <= 15 and the entry-16 row and column come from
+// `border` (MX_BORDER_FLOATS, wave-uniform) on the vector units:
+//   v_c += phi_16(x) sum_{j<=16} C_c[16][j] phi_j(y) + phi_16(y) sum_{i<16} C_c[i][16] phi_i(x).
 template <int K>
 __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, float inv, float xh, float yh,
-                                            float &vx, float &vy)
+                                            float &vx, float &vy, const float *__restrict__ border = nullptr)
 {
     constexpr int B = 2 * K + 1;
+    float px[17];
+    scaled_basis<K>(xh, px);
+#pragma unroll
+    for (int e = B; e < 17; ++e) px[e] = 0.f;
     f32x16 d0, d1;
-    mx_contract<K>(ahi, alo, xh, d0, d1);
+    mx_contract<K>(ahi, alo, px, d0, d1);
 
     // y basis (FP32, unscaled) while the matrix cores work: Py = entries
     // {0..3, 8..11}, Qy = {4..7, 12..15}; after the swaps Py serves column
     // block 0 and Qy block 1, entry q matching D register q (x rows) and
     // 8 + q (y rows)
-    float py[16];
+    float py[17];
     trig_basis<float, K>(yh, py);
 #pragma unroll
-    for (int e = B; e < 16; ++e) py[e] = 0.f;
+    for (int e = B; e < 17; ++e) py[e] = 0.f;
     float Py[8], Qy[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -239,6 +261,22 @@ __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, fl
     swap_halves(ay0, ay1);
     vx = (ax0 + ax1) * inv;
     vy = (ay0 + ay1) * inv;
+    if constexpr (K == 8) {
+        float r0 = 0.f, r1 = 0.f, s0 = 0.f, s1 = 0.f;
+#pragma unroll
+        for (int j = 0; j < 17; ++j) {
+            r0 = __builtin_fmaf(border[j], py[j], r0);
+            r1 = __builtin_fmaf(border[17 + j], py[j], r1);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            s0 = __builtin_fmaf(border[34 + i], px[i], s0);
+            s1 = __builtin_fmaf(border[50 + i], px[i], s1);
+        }
+        const float p16 = px[16] * 0x1p-8f;  // phi_16(x), exact
+        vx = __builtin_fmaf(r0, p16, __builtin_fmaf(s0, py[16], vx));
+        vy = __builtin_fmaf(r1, p16, __builtin_fmaf(s1, py[16], vy));
+    }
 }
 
 // Disk, psi = chi psi_F with chi = (1 - r^2)^2 (K <= 4, B <= 9): rows 8f + j
@@ -255,8 +293,12 @@ __device__ __forceinline__ void mx_velocity_disk(const h16x8 ahi, const h16x8 al
 {
     constexpr int B = 2 * K + 1;
     static_assert(K >= 1 && B <= 9, "disk rows");
+    float px[16];
+    scaled_basis<K>(xh, px);
+#pragma unroll
+    for (int e = B; e < 16; ++e) px[e] = 0.f;
     f32x16 d0, d1;
-    mx_contract<K>(ahi, alo, xh, d0, d1);
+    mx_contract<K>(ahi, alo, px, d0, d1);
     float py[16];
     trig_basis<float, K>(yh, py);
 #pragma unroll
@@ -324,6 +366,14 @@ struct FixCoord {
     }
 };
 
+// LDS writes of one wave visible to the same wave's later reads.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ void load_set(const unsigned char *__restrict__ set, int lane, h16x8 &ahi, h16x8 &alo,
                                          float &inv)
 {
@@ -342,8 +392,13 @@ __device__ __forceinline__ void load_set(const unsigned char *__restrict__ set, 
 template <int K, bool MT>
 __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
 {
+    // K = 8: the border coefficients of the wave's parameter set, re-read from
+    // LDS at every step (broadcast) rather than held in 66 registers
+    constexpr int NBD = MX_BORDER_FLOATS + 2;
+    __shared__ float s_border[K == 8 ? 4 * NBD : 4];
     const TimeArgs<float> &a = m.t;
     const int lane = threadIdx.x & 63;
+    float *my_border = s_border + (K == 8 ? (threadIdx.x >> 6) * NBD : 0);
     int cur_b = -1;
     h16x8 ahi = {}, alo = {};
     float inv = 0.f;
@@ -373,7 +428,14 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
             seed = a.seed_arr[b];
         }
         if (b != cur_b) {
-            load_set(m.sets + (int64_t)b * MX_SET_BYTES, lane, ahi, alo, inv);
+            const unsigned char *set = m.sets + (int64_t)b * MX_SET_BYTES;
+            load_set(set, lane, ahi, alo, inv);
+            if constexpr (K == 8) {
+                const float *src = reinterpret_cast<const float *>(set + MX_BORDER_OFFSET);
+                wave_lds_sync();
+                for (int e = lane; e < NBD; e += 64) my_border[e] = src[e];
+                wave_lds_sync();
+            }
             cur_b = b;
         }
         const int64_t cpo = (np + 63) >> 6;
@@ -389,7 +451,8 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
 
         auto step = [&](float z0, float z1) {
             float vx, vy;
-            mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy);
+            if constexpr (K == 8) __asm__ volatile("" ::: "memory");  // re-read the borders every step
+            mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy, my_border);
             x.advance(vx + a.v0x, z0, m.fx);
             y.advance(vy + a.v0y, z1, m.fx);
         };
@@ -436,17 +499,23 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
 template <int K>
 __global__ __launch_bounds__(256) void k_step_mx(const MxStepArgs a)
 {
+    __shared__ float s_border[MX_BORDER_FLOATS + 2];
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const bool act = e < a.count;
     h16x8 ahi, alo;
     float inv;
     load_set(a.set, lane, ahi, alo, inv);
+    if constexpr (K == 8) {
+        if (threadIdx.x < MX_BORDER_FLOATS + 2)
+            s_border[threadIdx.x] = reinterpret_cast<const float *>(a.set + MX_BORDER_OFFSET)[threadIdx.x];
+        __syncthreads();
+    }
     FixCoord x, y;
     x.set(act ? a.X[2 * e] : 0.0);
     y.set(act ? a.X[2 * e + 1] : 0.0);
     float vx, vy;
-    mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy);
+    mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy, s_border);
     if (!act) return;
     if (a.V) {
         a.V[2 * e] = (double)(vx + a.v0x);
@@ -527,6 +596,7 @@ static hipError_t dispatch_mx(int K, F &&f)
     case 5: return f(std::integral_constant<int, 5>{});
     case 6: return f(std::integral_constant<int, 6>{});
     case 7: return f(std::integral_constant<int, 7>{});
+    case 8: return f(std::integral_constant<int, 8>{});
     default: return hipErrorInvalidValue;
     }
 }

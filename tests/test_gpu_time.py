@@ -394,13 +394,14 @@ def test_ragged_particle_counts_fp32(pm, ctx, orc, engine_of, engine, Np):
         assert np.all(np_(v) == 0)
 
 
-def test_teacher_forced_steps_largest_small_k(pm, ctx, orc, engine_of):
-    """K = 7, the largest cutoff of the small-K matrix-core path (B = 15 of
-    16 tile entries), in teacher-forced steps against the oracle."""
+@pytest.mark.parametrize("K", [7, 8])
+def test_teacher_forced_steps_largest_small_k(pm, ctx, orc, engine_of, K):
+    """The largest cutoffs of the small-K matrix-core path in teacher-forced
+    steps against the oracle: K = 7 (B = 15 of 16 tile entries) and K = 8
+    (the tile plus the entry-16 row and column on the vector units)."""
     engine_of("mfma")
-    K = 7
     modes = W.torus_modes(K)
-    rng = np.random.default_rng(77)
+    rng = np.random.default_rng(70 + K)
     u = W.draw_prior(modes, rng)
     kappa, dt, seed = 0.01, 1e-3, 5
     X = rng.random((700, 2))
@@ -411,7 +412,7 @@ def test_teacher_forced_steps_largest_small_k(pm, ctx, orc, engine_of):
     Y = np_(prob.step(u, X, n, i, j, kappa, dt, seed))
     Yr = orc.step("torus", modes, u, kappa, dt, seed, X, n, i, j)
     d = tdist(Y, Yr)
-    print("teacher-forced K=7 mfma: max %.2e" % d.max())
+    print("teacher-forced K=%d mfma: max %.2e" % (K, d.max()))
     assert np.max(d) <= 1e-6
 
 
