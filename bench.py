@@ -40,8 +40,8 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 COUNTER_TRAFFIC = {
     # k_time<float,6,3>: FETCH 164.50 KiB x 2 + WRITE 77,480.78 KiB x 1
     "valu": (79_677_216, "fb42326f53cd55ae5fe7e78b87d1b5a828335e4ab4d5dd6d85cfd2fc29352d35"),
-    # k_time_mx<6>: FETCH 68.38 KiB x 2 + WRITE 79,172.34 KiB x 1
-    "mfma": (81_212_512, "19b7d79a2d25330cb31ec25c49032f38a3bc7665619096c340428eeefd690b1f"),
+    # k_time_mx<6>: FETCH 65.25 KiB x 2 + WRITE 79,172.34 KiB x 1
+    "mfma": (81_206_112, "6163ebf85579e5b63314e9f68721a6fbaef4d540bcbeb0763e9521bda725e8c9"),
 }
 KERNEL_SOURCES = {
     "valu": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
