@@ -23,11 +23,13 @@
 // four j, and two butterfly steps over g complete the sums.  Particle p of a
 // wave lives in lane p (the chunk layout of the time kernel).
 #include "pm_kernels.h"
+#include "pm_split.h"
 
 namespace pm {
 
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // Fold: u -> split FP16 coefficient tiles.
@@ -240,18 +242,26 @@ __device__ __forceinline__ void hk_velocity_block(const unsigned char *__restric
         pyl[rb] = __shfl(yl, src);
     }
     // B operands: phi_{32 kt + 8 g + e}(x) x 2^8 split into FP16 pairs;
-    // frequencies 16 kt + 4 g + d (d = 0..4)
+    // frequencies 16 kt + 4 g + d (d = 0..4).  The run starts scaled by 2^8
+    // and rotates by the unscaled angle, so every value carries the scale
+    // exactly (a power of two commutes with each rounding).
     f16x8 bh[KT][RB], bl[KT][RB];
+    constexpr float SCL = (float)(1 << HK_BASIS_SHIFT);
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
         Run<5> rx;
         run_init(rx, 4 * g, 16, pxh[rb], pxl[rb]);
 #pragma unroll
+        for (int d = 0; d < 5; ++d) {
+            rx.c[d] *= SCL;
+            rx.s[d] *= SCL;
+        }
+#pragma unroll
         for (int kt = 0; kt < KT; ++kt) {
             if (kt) run_next(rx);
             const int i0 = 32 * kt + 8 * g;
             float o[8];
-            o[0] = (i0 == 0) ? 1.f : rx.s[0];
+            o[0] = (i0 == 0) ? SCL : rx.s[0];
             o[1] = rx.c[1];
             o[2] = rx.s[1];
             o[3] = rx.c[2];
@@ -261,13 +271,11 @@ __device__ __forceinline__ void hk_velocity_block(const unsigned char *__restric
             o[7] = rx.c[4];
             // entries past B meet zero coefficient rows, so their (finite)
             // values do not matter and need no masking
+            uint32_t hw[4], lw[4];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float v = o[e] * (float)(1 << HK_BASIS_SHIFT);
-                const _Float16 hi = (_Float16)v;
-                bh[kt][rb][e] = hi;
-                bl[kt][rb][e] = (_Float16)(v - (float)hi);
-            }
+            for (int d = 0; d < 4; ++d) split_pair(o[2 * d], o[2 * d + 1], hw[d], lw[d]);
+            bh[kt][rb] = __builtin_bit_cast(f16x8, (u32x4){hw[0], hw[1], hw[2], hw[3]});
+            bl[kt][rb] = __builtin_bit_cast(f16x8, (u32x4){lw[0], lw[1], lw[2], lw[3]});
         }
     }
     // y basis runs: frequencies 8 nt + 2 g + d (d = 0..2), one run per rb

@@ -31,6 +31,7 @@
 // particle in a fixed order, so the result is identical in every launch
 // shape.
 #include "pm_mx.h"
+#include "pm_split.h"
 #include "pm_walk.h"
 
 namespace pm {
@@ -158,24 +159,10 @@ __device__ __forceinline__ void scaled_basis(float s, float *phi)
     }
 }
 
-// FP16 pairs of two values: hi = (f16(v0), f16(v1)) and lo = (f16(v0 - hi0),
-// f16(v1 - hi1)), each half written in place by a mixed-precision FMA (v * 1
-// - hi is exact in the FMA, so lo is the correctly rounded remainder).
-__device__ __forceinline__ void split_pair(float v0, float v1, uint32_t &hi, uint32_t &lo)
-{
-    uint32_t h, l;
-    asm("v_fma_mixlo_f16 %0, %1, 1.0, 0" : "=v"(h) : "v"(v0));
-    asm("v_fma_mixhi_f16 %0, %1, 1.0, 0" : "+v"(h) : "v"(v1));
-    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(l) : "v"(v0), "v"(h));
-    asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "+v"(l) : "v"(v1), "v"(h));
-    hi = h;
-    lo = l;
-}
-
 // The contraction W = A^T Phi_x for the 64 particles of a wave: x basis x 2^8
 // (px, from scaled_basis) split into FP16 pairs (P holds entries 0..7, Q
-// 8..15; entries past B are zero), the half-wave swaps that make P the B operand of column block 0
-// (particles 0..31) and Q that of block 1 (32..63), and the three split
+// 8..15; entries past B are zero), the half-wave swaps that make P the B operand of
+// column block 0 (particles 0..31) and Q that of block 1 (32..63), and the three split
 // products per block.
 template <int K>
 __device__ __forceinline__ void mx_contract(const h16x8 ahi, const h16x8 alo, const float *px, f32x16 &d0,
