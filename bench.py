@@ -40,8 +40,8 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 COUNTER_TRAFFIC = {
     # k_time<float,6,3>: FETCH 164.50 KiB x 2 + WRITE 77,480.78 KiB x 1
     "valu": (79_677_216, "fb42326f53cd55ae5fe7e78b87d1b5a828335e4ab4d5dd6d85cfd2fc29352d35"),
-    # k_time_mx<6>: FETCH 64.38 KiB x 2 + WRITE 79,172.34 KiB x 1
-    "mfma": (81_204_320, "fa05957619b8d52c14e2d6f8873e803eb30e820685561661de1e666b35d012cc"),
+    # k_time_mx<6>: FETCH 64.19 KiB x 2 + WRITE 79,172.34 KiB x 1
+    "mfma": (81_203_936, "020f9004a9e67e3ca6ff92f8cfcc7c6c19425d3e934daa04546404780c12adc1"),
 }
 KERNEL_SOURCES = {
     "valu": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
