@@ -86,9 +86,10 @@ __global__ __launch_bounds__(256) void k_pack_mx(const MxPackArgs a, unsigned ch
         const int lane = t >> 3, e = t & 7;
         const int row = lane & 31, i = 8 * (lane >> 5) + e;
         int comp, j;
-        if (nf == 2) {  // torus: rows 0..15 Cx, 16..31 Cy
+        if (nf == 2) {  // torus: rows 0..15 Cx, 16..31 Cy; row 8(q/4) + 4h + q%4 holds j = 2q + h
             comp = row >> 4;
-            j = row & 15;
+            const int r = row & 15;
+            j = 2 * (4 * (r >> 3) + (r & 3)) + ((r >> 2) & 1);
         } else {  // disk: rows 8f + j (j < 8) and 24 + f (j = 8) for form f
             comp = row < 24 ? row >> 3 : (row < 27 ? row - 24 : -1);
             j = row < 24 ? row & 7 : 8;
@@ -204,8 +205,12 @@ __device__ __forceinline__ void mx_contract(const h16x8 ahi, const h16x8 alo, co
     d1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(alo, b1h, d1, 0, 0, 0);
 }
 
-// Torus: rows q < 16 are Cx[.][j = q], rows q >= 16 Cy[.][j = q - 16].  At
-// K = 8 the tile holds i, j <= 15 and the entry-16 row and column come from
+// Torus: rows r < 16 hold Cx[.][j], rows r >= 16 Cy[.][j], with tile row
+// r mod 16 = 8 (q / 4) + 4 h + q mod 4 holding j = 2 q + h (k_pack_mx): D
+// register q of a lower-half lane then meets y entry 2q and the same
+// register of an upper-half lane entry 2q + 1, so the registers q with
+// 2q >= B hold zero rows in both halves and drop out.  At K = 8 the tile
+// holds i, j <= 15 and the entry-16 row and column come from
 // `border` (MX_BORDER_FLOATS, wave-uniform) on the vector units:
 //   v_c += phi_16(x) sum_{j<=16} C_c[16][j] phi_j(y) + phi_16(y) sum_{i<16} C_c[i][16] phi_i(x).
 template <int K>
@@ -220,25 +225,25 @@ __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, fl
     f32x16 d0, d1;
     mx_contract<K>(ahi, alo, px, d0, d1);
 
-    // y basis (FP32, unscaled) while the matrix cores work: Py = entries
-    // {0..3, 8..11}, Qy = {4..7, 12..15}; after the swaps Py serves column
-    // block 0 and Qy block 1, entry q matching D register q (x rows) and
-    // 8 + q (y rows)
+    // y basis (FP32, unscaled) while the matrix cores work: Py = entries 2q,
+    // Qy = entries 2q + 1; after the swaps Py serves column block 0 and Qy
+    // block 1, matching D register q (x rows) and 8 + q (y rows)
+    constexpr int BT = B < 16 ? B : 16;  // y entries in the tile
+    constexpr int NQ = (BT + 1) / 2;      // D registers with a nonzero row
     float py[17];
     cheb_basis<K>(yh, 1.f, py);
 #pragma unroll
     for (int e = B; e < 17; ++e) py[e] = 0.f;
-    float Py[8], Qy[8];
+    float Py[NQ], Qy[NQ];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int jl = (q < 4) ? q : q + 4;  // 0..3, 8..11
-        Py[q] = py[jl];
-        Qy[q] = py[jl + 4];
+    for (int q = 0; q < NQ; ++q) {
+        Py[q] = py[2 * q];
+        Qy[q] = 2 * q + 1 < BT ? py[2 * q + 1] : 0.f;
         swap_halves(Py[q], Qy[q]);
     }
     float ax0 = 0.f, ay0 = 0.f, ax1 = 0.f, ay1 = 0.f;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         ax0 = __builtin_fmaf(d0[q], Py[q], ax0);
         ay0 = __builtin_fmaf(d0[8 + q], Py[q], ay0);
         ax1 = __builtin_fmaf(d1[q], Qy[q], ax1);
