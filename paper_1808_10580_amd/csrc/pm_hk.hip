@@ -161,21 +161,35 @@ __device__ __forceinline__ float hk_phase(int n, float sh, float sl)
 
 // A lane needs, per particle, runs of D consecutive frequencies n0 + d that
 // repeat every S frequencies (one run per tile).  The first run and the
-// rotation by S come from the hardware sine/cosine; each further run is the
-// previous one rotated by the angle addition theorems,
-//   cos((n+S)t) = cos(nt) cos(St) - sin(nt) sin(St),
-//   sin((n+S)t) = sin(nt) cos(St) + cos(nt) sin(St).
+// rotation by S come from the hardware sine/cosine; each further run follows
+// from the two before it by the three-term recurrences
+//   cos((n+S)t) = 2 cos(St) cos(nt) - cos((n-S)t),
+//   sin((n+S)t) = 2 cos(St) sin(nt) - sin((n-S)t),
+// one FMA per value, the run before the first one being the first rotated
+// back by S (angle subtraction).  A run may start scaled by a power of two
+// (the x basis), which every later run then carries exactly.
 template <int D>
 struct Run {
-    float c[D], s[D], cS, sS;
+    float c[D], s[D];    // frequencies n0 + d + mS
+    float pc[D], ps[D];  // frequencies n0 + d + (m - 1)S
+    float t;             // 2 cos(St)
 };
 
 template <int D>
-__device__ __forceinline__ void run_init(Run<D> &r, int n0, int S, float sh, float sl)
+__device__ __forceinline__ void run_init(Run<D> &r, int n0, int S, float sh, float sl, float scale)
 {
+    float sS, cS;
+    sincos_rev(hk_phase(S, sh, sl), sS, cS);
+    r.t = cS + cS;
 #pragma unroll
-    for (int d = 0; d < D; ++d) sincos_rev(hk_phase(n0 + d, sh, sl), r.s[d], r.c[d]);
-    sincos_rev(hk_phase(S, sh, sl), r.sS, r.cS);
+    for (int d = 0; d < D; ++d) {
+        float sn, cn;
+        sincos_rev(hk_phase(n0 + d, sh, sl), sn, cn);
+        r.c[d] = cn * scale;
+        r.s[d] = sn * scale;
+        r.pc[d] = __builtin_fmaf(r.c[d], cS, r.s[d] * sS);
+        r.ps[d] = __builtin_fmaf(r.s[d], cS, -(r.c[d] * sS));
+    }
 }
 
 template <int D>
@@ -183,8 +197,10 @@ __device__ __forceinline__ void run_next(Run<D> &r)
 {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        const float c = __builtin_fmaf(r.c[d], r.cS, -(r.s[d] * r.sS));
-        const float s = __builtin_fmaf(r.s[d], r.cS, r.c[d] * r.sS);
+        const float c = __builtin_fmaf(r.t, r.c[d], -r.pc[d]);
+        const float s = __builtin_fmaf(r.t, r.s[d], -r.ps[d]);
+        r.pc[d] = r.c[d];
+        r.ps[d] = r.s[d];
         r.c[d] = c;
         r.s[d] = s;
     }
@@ -243,19 +259,14 @@ __device__ __forceinline__ void hk_velocity_block(const unsigned char *__restric
     }
     // B operands: phi_{32 kt + 8 g + e}(x) x 2^8 split into FP16 pairs;
     // frequencies 16 kt + 4 g + d (d = 0..4).  The run starts scaled by 2^8
-    // and rotates by the unscaled angle, so every value carries the scale
-    // exactly (a power of two commutes with each rounding).
+    // and the recurrence coefficient 2 cos(16t) is unscaled, so every value
+    // carries the scale exactly (a power of two commutes with each rounding).
     f16x8 bh[KT][RB], bl[KT][RB];
     constexpr float SCL = (float)(1 << HK_BASIS_SHIFT);
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
         Run<5> rx;
-        run_init(rx, 4 * g, 16, pxh[rb], pxl[rb]);
-#pragma unroll
-        for (int d = 0; d < 5; ++d) {
-            rx.c[d] *= SCL;
-            rx.s[d] *= SCL;
-        }
+        run_init(rx, 4 * g, 16, pxh[rb], pxl[rb], SCL);
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt) {
             if (kt) run_next(rx);
@@ -281,7 +292,7 @@ __device__ __forceinline__ void hk_velocity_block(const unsigned char *__restric
     // y basis runs: frequencies 8 nt + 2 g + d (d = 0..2), one run per rb
     Run<3> ry[RB];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) run_init(ry[rb], 2 * g, 8, pyh[rb], pyl[rb]);
+    for (int rb = 0; rb < RB; ++rb) run_init(ry[rb], 2 * g, 8, pyh[rb], pyl[rb], 1.f);
 
     __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0) expcnt(0) lgkmcnt(0): stage 0 is in LDS
     __syncthreads();
