@@ -59,6 +59,34 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     return U4{c0, c1, c2, c3};
 }
 
+// The same generator for counters (c0, c1, c2, 0) whose words c0 and c2 are
+// uniform across the wave (the time kernels' step block and observation).
+// Then the second round's new word 0, the first round's new word 2 and the
+// product of the second and third rounds that they feed are uniform as
+// well: those exclusive ors are plain ones, which the compiler places on the
+// scalar unit together with the products (the three-input vector form would
+// pull them onto the vector units).  Bitwise the same words as philox4x32_10.
+__device__ __forceinline__ U4 philox4x32_10_wu(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t k0, uint32_t k1)
+{
+    uint32_t c3 = 0u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
+        const uint32_t n0 = r == 1 ? hi1 ^ c1 ^ k0 : __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
+        const uint32_t n2 = r == 0 ? hi0 ^ c3 ^ k1 : __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
 // Box-Muller on two 24-bit uniforms: ua = ((wa>>8)+1) 2^-24 in (0,1],
 // ub = (wb>>8) 2^-24 in [0,1), both exact in FP32 and FP64.
 // v_log_f32 is log2, v_sin_f32/v_cos_f32 take revolutions.

@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
                 T z0[PPL], z1[PPL], z2[PPL], z3[PPL];
 #pragma unroll
                 for (int p = 0; p < PPL; ++p) {
-                    const U4 w = philox4x32_10((uint32_t)(n >> 1), pi[p], pj[p], 0u, k0, k1);
+                    const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi[p], pj[p], k0, k1);
                     box_muller(w.x, w.y, z0[p], z1[p]);
                     box_muller(w.z, w.w, z2[p], z3[p]);
                 }
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
                 T z0[PPL], z1[PPL];
 #pragma unroll
                 for (int p = 0; p < PPL; ++p) {
-                    const U4 w = philox4x32_10((uint32_t)(n >> 1), pi[p], pj[p], 0u, k0, k1);
+                    const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi[p], pj[p], k0, k1);
                     box_muller(w.x, w.y, z0[p], z1[p]);
                 }
                 step(z0, z1);
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
                 T z0[PPL], z1[PPL], z2[PPL], z3[PPL];
 #pragma unroll
                 for (int p = 0; p < PPL; ++p) {
-                    const U4 w = philox4x32_10((uint32_t)(n >> 1), pi[p], pj[p], 0u, k0, k1);
+                    const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi[p], pj[p], k0, k1);
                     box_muller(w.x, w.y, z0[p], z1[p]);
                     box_muller(w.z, w.w, z2[p], z3[p]);
                 }
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
                 T z0[PPL], z1[PPL];
 #pragma unroll
                 for (int p = 0; p < PPL; ++p) {
-                    const U4 w = philox4x32_10((uint32_t)(n >> 1), pi[p], pj[p], 0u, k0, k1);
+                    const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi[p], pj[p], k0, k1);
                     box_muller(w.x, w.y, z0[p], z1[p]);
                 }
                 step(z0, z1);

@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
         readout(0);
         int64_t n = 0;
         for (; n + 1 < a.n_steps; n += 2) {
-            const U4 w = philox4x32_10((uint32_t)(n >> 1), pi, pj, 0u, k0, k1);
+            const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi, pj, k0, k1);
             float z0, z1, z2, z3;
             box_muller(w.x, w.y, z0, z1);
             box_muller(w.z, w.w, z2, z3);
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
             readout(n + 2);
         }
         if (n < a.n_steps) {
-            const U4 w = philox4x32_10((uint32_t)(n >> 1), pi, pj, 0u, k0, k1);
+            const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi, pj, k0, k1);
             float z0, z1;
             box_muller(w.x, w.y, z0, z1);
             step(z0, z1);
