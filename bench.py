@@ -38,10 +38,10 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 # reported when the sources still hash to the recorded value, else null.
 # Per velocity engine: (bytes per launch, SHA-256 of the kernel's sources).
 COUNTER_TRAFFIC = {
-    # k_time<float,6,3>: FETCH 161.13 KiB x 2 + WRITE 77,480.78 KiB x 1
-    "valu": (79_670_304, "f4e175543267bc1656e3c3e4e79293539b1504c652adf8007f559adf9f1c7025"),
-    # k_time_mx<6>: FETCH 59.94 KiB x 2 + WRITE 79,172.34 KiB x 1
-    "mfma": (81_195_232, "0f6cb4017be4b4e7a5429f880e5323e1a4d1e1c0c35a1a83a76908ce0a8feee1"),
+    # k_time<float,6,3>: FETCH 156.75 KiB x 2 + WRITE 77,480.78 KiB x 1
+    "valu": (79_661_344, "1953a56cc2e1e185d730e0e0f3cabb1c918d8565f6fe3dc38fd8258264760cf2"),
+    # k_time_mx<6>: FETCH 60.06 KiB x 2 + WRITE 79,172.34 KiB x 1
+    "mfma": (81_195_488, "4aca7a1cefd627c618f0ebf1f714beaf68449d47e20fb69cb9fb165b66a9e629"),
 }
 KERNEL_SOURCES = {
     "valu": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
