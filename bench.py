@@ -343,8 +343,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the particle map's "
-              "multi-GPU sharding is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the particle map "
+              "over several GPUs (one process per GPU, observations and particles split across ranks) "
+              "is not built.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "torus-modes-sweep":
         bench_modes_sweep(args)

@@ -7,7 +7,7 @@
  *     y = h_L W_{L+1} + b_{L+1},  G(u) ~ y * out_std + out_mean,
  * with GELU(z) = z Phi(z) (exact, erf form).  It is trained on (u, G(u))
  * pairs produced by the particle map itself and serves as the first stage of
- * delayed-acceptance pCN; the particle map stays the judge of acceptance.
+ * delayed-acceptance pCN; the particle map still decides acceptance.
  *
  * Arithmetic: matrix products run on the MFMA units in BF16 with FP32
  * accumulation (v_mfma_f32_16x16x32_bf16); master weights, Adam moments,
