@@ -98,7 +98,9 @@ def kernel_roofline(engine: str, K: int, fl: int, steps: float, kern_s: float, t
 def flops_per_particle_step(K: int) -> int:
     """Algorithmic FP32 FLOPs of one Euler-Maruyama step of the time kernel
     (FMA = 2).  Trig basis: per axis K-1 angle-addition harmonics of 2 mul +
-    2 FMA.  Velocity: two bilinear forms phi(x)^T C phi(y) over B = 2K+1
+    2 FMA (the per-harmonic cost the count is defined with; the kernels now
+    take the harmonics from the three-term recurrence, 4 (K-1) FLOP per axis,
+    so they execute 20 FLOP fewer than counted at K = 6).  Velocity: two bilinear forms phi(x)^T C phi(y) over B = 2K+1
     basis functions per axis; row j = 0 carries only the y form (1 mul +
     (B-2) FMA), rows j >= 1 carry both (x: B-1 FMA, y: 1 mul + B-2 FMA) and
     two FMAs into (v_x, v_y).  Update: 1 add + 2 FMA per axis.  Box-Muller
