@@ -43,7 +43,20 @@ COUNTER_TRAFFIC = {
     # k_time_mx<6>: FETCH 60.06 KiB x 2 + WRITE 79,172.34 KiB x 1
     "mfma": (81_195_488, "4aca7a1cefd627c618f0ebf1f714beaf68449d47e20fb69cb9fb165b66a9e629"),
 }
+# The same for the dominant kernel of the other workloads (bench.py
+# --workload ...), keyed by (workload, velocity engine): (bytes per launch,
+# SHA-256 of the sources, source list).
+OTHER_TRAFFIC = {
+    # k_time_hk<6,2>: FETCH 918.69 KiB x 2 + WRITE 40,702.84 KiB x 1
+    ("torus-k80-turbulent", "mfma"): (43_561_184, "310429af8df2502301e9988b4708f97f143cd342e07191f62799a99be583c96b", "hk"),
+    # k_dirichlet_mx<4,0>: FETCH 74.25 KiB x 2 + WRITE 185,317.13 KiB x 1
+    ("disk-dirichlet", "mfma"): (189_916_800, "4aca7a1cefd627c618f0ebf1f714beaf68449d47e20fb69cb9fb165b66a9e629", "mfma"),
+    # k_dirichlet<float,4,0,SC>: FETCH 89.94 KiB x 2 + WRITE 185,459.97 KiB x 1
+    ("disk-dirichlet", "valu"): (190_094_400, "1953a56cc2e1e185d730e0e0f3cabb1c918d8565f6fe3dc38fd8258264760cf2", "valu"),
+}
 KERNEL_SOURCES = {
+    "hk": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
+           "paper_1808_10580_amd/csrc/pm_split.h", "paper_1808_10580_amd/csrc/pm_hk.hip"),
     "valu": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
              "paper_1808_10580_amd/csrc/pm_walk.h", "paper_1808_10580_amd/csrc/pm_kernels.hip"),
     "mfma": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
@@ -71,6 +84,24 @@ def counter_traffic(engine: str):
     if nbytes is None or kernel_sources_sha256(engine) != sha:
         return None
     return nbytes
+
+
+def other_traffic(workload: str, engine: str):
+    nbytes, sha, src = OTHER_TRAFFIC.get((workload, engine), (None, "", "valu"))
+    if nbytes is None or kernel_sources_sha256(src) != sha:
+        return None
+    return nbytes
+
+
+def calibration_copy(torch, dev, mib: int):
+    """One plain device-to-device copy of a known size: the reference that
+    scales the profiler's FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    if mib > 0:
+        src = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
 
 def engine_in_use(pm, engine_arg: str, K: int, domain: str = "torus") -> str:
@@ -227,6 +258,7 @@ def bench_other(args):
     ctx.set_velocity_engine(args.engine)
     name = args.workload
     cpu = None
+    calibration_copy(torch, dev, args.copy_mib)
     if name == "torus-k80-turbulent":
         wl = W.turbulent_k80()
         prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
@@ -243,6 +275,7 @@ def bench_other(args):
         fl = flops_per_particle_step_mfma(K)
         rl = {"bound": "mfma", "peak": 2500.0, "unit": "TFLOP/s", "kernel": f"k_time_hk<{(2 * K + 32) // 32}>",
               "flop_per_particle_step": fl, "dtype_of_peak": "fp16 dense"}
+        traffic = other_traffic(name, "mfma")
         desc = ("torus-k80-turbulent: |k|_2<=80 (10,040 modes, 20,080 coefficients), kappa=3e-5, 2 points x 1e5 "
                 "particles, 4,800 steps (dt=1/9600) read out at 13 times in [0, 0.5], FP32 states, split-FP16 "
                 "matrix-core velocity")
@@ -276,6 +309,7 @@ def bench_other(args):
         rl = {"bound": "alu", "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
               "kernel": f"k_dirichlet_mx<{K}>" if eng == "mfma" else f"k_dirichlet<float,{K}>",
               "flop_per_particle_step": fl, "velocity_engine": eng}
+        traffic = other_traffic(name, eng)
         desc = ("disk-dirichlet: unit disk, 64-coefficient stream function x (1-r^2)^2, kappa=0.02, g=cos 3phi, "
                 "f=-1, 25 points x 5e4 particles, dt=1e-4, walks until exit, FP32 states + FP64 exit test")
     elif name == "torus-k6-batch":
@@ -311,8 +345,8 @@ def bench_other(args):
         rl = kernel_roofline(rl["engine"], K, fl, steps_per_map, kern_s, None)
     else:
         achieved = fl * steps_per_map / kern_s / 1e12
-        rl.update({"achieved": round(achieved, 3), "frac": round(achieved / rl["peak"], 4), "traffic": None,
-                   "kernel_ms": round(kern_s * 1e3, 3)})
+        rl.update({"achieved": round(achieved, 3), "frac": round(achieved / rl["peak"], 4), "traffic": traffic,
+                   "traffic_unit": "bytes per launch", "kernel_ms": round(kern_s * 1e3, 3)})
     out = {"metric": "particle-steps/s at 1 GPU", "value": steps_per_map * args.steps / elapsed,
            "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
@@ -372,12 +406,7 @@ def main():
     engine = engine_in_use(pm, args.engine, K)
     steps_per_map = wl.n_obs * wl.n_particles * wl.n_steps
 
-    if args.copy_mib > 0:
-        src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calibration_copy(torch, dev, args.copy_mib)
     tuned = None
     if engine == "valu" and not args.no_autotune and args.ppl == 0:
         # untimed setup: pick the fastest vector-kernel variant (results are identical for all)
