@@ -283,15 +283,15 @@ int pm_set_tuning(pm_ctx *ctx, int particles_per_lane, int coef_source);
  *     both, the bilinear forms of 64 particles are one matrix-core
  *     contraction (v_mfma_f32_32x32x16_f16 on coefficients and x basis
  *     split into FP16 hi + lo halves, three products, FP32 accumulation:
- *     velocity errors near 5e-7 of max |v|, paths within the FP32 error
+ *     velocity errors near 1e-6 of max |v|, paths within the FP32 error
  *     contract);
  *   PM_ENGINE_VALU: FP32 fused multiply-adds on the vector units (the
  *     kernel that pm_set_tuning and pm_autotune_time tune).
- * On the torus the matrix-core kernels keep particle coordinates as 32-bit
- * fractions of the period (resolution 2^-32, the wrap by modular overflow)
- * and apply when sqrt(2 kappa dt) <= 0.05; larger steps run on the vector
- * units.  On the disk they keep the vector engine's double-float
- * coordinates.  The two engines round differently, so their results agree
+ * The matrix-core kernels keep particle coordinates as 32-bit fixed-point
+ * numbers: on the torus fractions of the period (resolution 2^-32, the wrap
+ * by modular overflow), on the disk multiples of 2^-30 with each step's
+ * increment clamped to 1/2 per axis.  They apply when sqrt(2 kappa dt) <=
+ * 0.05; larger steps run on the vector units.  The two engines round differently, so their results agree
  * to that contract, not bit for bit; each is deterministic.  FP64 problems,
  * the square and larger K ignore the setting.  Returns PM_EINVAL for another
  * value or a closed context. */

@@ -180,9 +180,8 @@ StepConsts<T> step_consts(double dt, double kappa)
 
 // The same constants in units of 2^-32 of the period, for the fixed-point
 // coordinates of the small-K matrix-core kernels.
-StepConsts<float> fixed_consts(double dt, double kappa)
+StepConsts<float> fixed_consts(double dt, double kappa, double S = 4294967296.0)
 {
-    const double S = 4294967296.0;
     StepConsts<float> c;
     c.dth = (float)(dt * S);
     c.dtl = (float)(dt * S - (double)c.dth);
@@ -581,7 +580,8 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
 {
     // the disk's FP32 walk runs the matrix-core velocity where it applies
     bool mx = false;
-    if constexpr (std::is_same<T, float>::value) mx = p->domain == PM_DISK && n_src == 0 && use_mx(c, p);
+    if constexpr (std::is_same<T, float>::value)
+        mx = p->domain == PM_DISK && n_src == 0 && use_mx(c, p) && mx_step_ok(dt, kappa);
     T *coef = nullptr;
     int64_t cstride = 0;
     const unsigned char *mx_set = nullptr;
@@ -677,7 +677,9 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     a.pout = pools[0];
     auto launch = [&]() -> hipError_t {
         if constexpr (std::is_same<T, float>::value) {
-            if (mx) return launch_dirichlet_mx(a, mx_set, p->K, fk, c->n_cu, c->dir_bpc, c->stream);
+            if (mx)
+                return launch_dirichlet_mx(a, fixed_consts(dt, kappa, std::ldexp(1.0, MX_DISK_SHIFT)), mx_set, p->K, fk,
+                                           c->n_cu, c->dir_bpc, c->stream);
         }
         return launch_dirichlet<T>(a, p->K, fk, c->dir_src, c->n_cu, c->dir_bpc, p->domain, c->stream);
     };
@@ -1131,7 +1133,7 @@ static int step_mx(pm_ctx *c, const pm_problem *p, const double *u, int64_t coun
     a.i = i;
     a.j = j;
     a.seed = seed;
-    a.fx = fixed_consts(dt, kappa);
+    a.fx = fixed_consts(dt, kappa, p->domain == PM_DISK ? std::ldexp(1.0, MX_DISK_SHIFT) : 4294967296.0);
     a.sc = step_consts<float>(dt, kappa);
     a.v0x = (float)p->v0[0];
     a.v0y = (float)p->v0[1];
@@ -1152,7 +1154,7 @@ int pm_step(pm_ctx *c, const pm_problem *p, const double *u, int64_t count, cons
     if (!(std::isfinite(kappa) && kappa >= 0.0) || !finite_pos(dt)) return PM_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
     if (p->hk) return step_hk(c, p, u, count, X, n, i, j, kappa, dt, seed, Y, nullptr);
-    if (use_mx(c, p) && (p->domain == PM_DISK || mx_step_ok(dt, kappa)))
+    if (use_mx(c, p) && mx_step_ok(dt, kappa))
         return step_mx(c, p, u, count, X, n, i, j, kappa, dt, seed, Y, nullptr);
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);

@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void k_dirichlet(const DirArgs<T> a)
         for (int e = threadIdx.x; e < NC; e += blockDim.x) lds[e] = a.coef[e];
         __syncthreads();
     }
-    dirichlet_walk<T, FK, DOM>(a, [&](T xa, T ya, T &vx, T &vy) {
+    dirichlet_walk<T, FK, DOM, Coord<T>>(a, a.sc, [&](T xa, T ya, T &vx, T &vy) {
         T phx[B], phy[B];
         trig_basis<T, K>(xa, phx);
         trig_basis<T, K>(ya, phy);

@@ -43,6 +43,9 @@ struct MxPackArgs {
 // Usable while one step moves a particle by far less than half the period:
 // the C ABI takes this engine only for sqrt(2 kappa dt) <= MX_MAX_SIGMA.
 constexpr double MX_MAX_SIGMA = 0.05;
+// Disk coordinates of the matrix-core walk: signed 32-bit multiples of
+// 2^-MX_DISK_SHIFT (range +-2; a step is clamped to 1/2 per axis).
+constexpr int MX_DISK_SHIFT = 30;
 
 struct MxTimeArgs {
     TimeArgs<float> t;           // chunk layout, steps, readouts, outputs (t.coef, t.sc unused)
@@ -58,8 +61,8 @@ struct MxStepArgs {
     const uint32_t *i;
     const uint32_t *j;
     uint64_t seed;
-    StepConsts<float> fx;  // torus: dt (hi + lo) and sqrt(2 kappa dt), each x 2^32
-    StepConsts<float> sc;  // disk: the same unscaled (double-float coordinates)
+    StepConsts<float> fx;  // dt (hi + lo) and sqrt(2 kappa dt), each x 2^32 (torus) or 2^MX_DISK_SHIFT (disk)
+    StepConsts<float> sc;  // the same unscaled
     float v0x, v0y;
     double *Y;  // step mode
     double *V;  // velocity mode when non-null (n, i, j, Y unused)
@@ -68,7 +71,7 @@ struct MxStepArgs {
 hipError_t launch_pack_mx(const MxPackArgs &a, unsigned char *out, int n_sets, hipStream_t st);
 hipError_t launch_time_mx(const MxTimeArgs &a, int K, int n_cu, int bpc, hipStream_t st);
 hipError_t launch_step_mx(const MxStepArgs &a, int K, int domain, hipStream_t st);
-hipError_t launch_dirichlet_mx(const DirArgs<float> &a, const unsigned char *set, int K, int fk, int n_cu, int bpc,
-                               hipStream_t st);
+hipError_t launch_dirichlet_mx(const DirArgs<float> &a, const StepConsts<float> &fx, const unsigned char *set, int K,
+                               int fk, int n_cu, int bpc, hipStream_t st);
 
 }  // namespace pm

@@ -361,6 +361,34 @@ struct FixCoord {
     }
 };
 
+// Disk coordinate as a signed 32-bit multiple of 2^-30 (range +-2): the
+// increment of eq. (euler) is formed as on the torus in units of 2^-30 and
+// rounded to the nearest unit (9.3e-10, unbiased, below the FP32 velocity
+// error per step).  Each increment is clamped to 1/2, so a walker that starts
+// a step inside the unit disk stays inside +-1.5 and the coordinate never
+// wraps; only steps that would move a particle by more than half the radius,
+// far outside any usable time step, are affected.  The exit test reads the
+// exact FP64 value.
+struct DiskFix {
+    int32_t X;
+    __device__ __forceinline__ void set(double x) { X = (int32_t)llrint(x * 0x1p30); }
+    __device__ __forceinline__ float at() const { return (float)X * 0x1p-30f; }
+    __device__ __forceinline__ double value() const { return (double)X * 0x1p-30; }
+    __device__ __forceinline__ void advance(float vel, float z, const StepConsts<float> &c)
+    {
+        float d = __builtin_fmaf(-c.dtl, vel, c.sq * z);
+        d = __builtin_fmaf(-c.dth, vel, d);
+        d = __builtin_fminf(__builtin_fmaxf(d, -0x1p29f), 0x1p29f);
+        X += (int32_t)__builtin_rintf(d);
+    }
+    __device__ __forceinline__ void save(double &a, double &b) const
+    {
+        a = value();
+        b = 0.0;
+    }
+    __device__ __forceinline__ void load(double a, double) { X = (int32_t)llrint(a * 0x1p30); }
+};
+
 // LDS writes of one wave visible to the same wave's later reads.
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -534,18 +562,19 @@ __global__ __launch_bounds__(256) void k_step_mx(const MxStepArgs a)
 // Algorithm 2 on the disk with the matrix-core velocity (the walk, refills,
 // exits and compaction of the vector kernel).
 template <int K, int FK>
-__global__ __launch_bounds__(256) void k_dirichlet_mx(const DirArgs<float> a, const unsigned char *set)
+__global__ __launch_bounds__(256) void k_dirichlet_mx(const DirArgs<float> a, const StepConsts<float> fx,
+                                                      const unsigned char *set)
 {
     const int lane = threadIdx.x & 63;
     h16x8 ahi, alo;
     float inv;
     load_set(set, lane, ahi, alo, inv);
-    dirichlet_walk<float, FK, PM_DISK>(
-        a, [&](float xa, float ya, float &vx, float &vy) { mx_velocity_disk<K>(ahi, alo, inv, xa, ya, vx, vy); });
+    dirichlet_walk<float, FK, PM_DISK, DiskFix>(
+        a, fx, [&](float xa, float ya, float &vx, float &vy) { mx_velocity_disk<K>(ahi, alo, inv, xa, ya, vx, vy); });
 }
 
-// Teacher-forced steps and velocity on the disk (double-float coordinates,
-// no wrap).
+// Teacher-forced steps and velocity on the disk (the walk's fixed-point
+// coordinates, no wrap).
 template <int K>
 __global__ __launch_bounds__(256) void k_step_mx_disk(const MxStepArgs a)
 {
@@ -555,7 +584,7 @@ __global__ __launch_bounds__(256) void k_step_mx_disk(const MxStepArgs a)
     h16x8 ahi, alo;
     float inv;
     load_set(a.set, lane, ahi, alo, inv);
-    Coord<float> x, y;
+    DiskFix x, y;
     x.set(act ? a.X[2 * e] : 0.0);
     y.set(act ? a.X[2 * e + 1] : 0.0);
     float vx, vy;
@@ -571,8 +600,8 @@ __global__ __launch_bounds__(256) void k_step_mx_disk(const MxStepArgs a)
     float z0, z1;
     if ((n & 1) == 0) box_muller(w.x, w.y, z0, z1);
     else box_muller(w.z, w.w, z0, z1);
-    x.advance(vx + a.v0x, z0, a.sc);
-    y.advance(vy + a.v0y, z1, a.sc);
+    x.advance(vx + a.v0x, z0, a.fx);
+    y.advance(vy + a.v0y, z1, a.fx);
     a.Y[2 * e] = x.value();
     a.Y[2 * e + 1] = y.value();
 }
@@ -646,8 +675,8 @@ hipError_t launch_step_mx(const MxStepArgs &a, int K, int domain, hipStream_t st
     });
 }
 
-hipError_t launch_dirichlet_mx(const DirArgs<float> &a, const unsigned char *set, int K, int fk, int n_cu, int bpc,
-                               hipStream_t st)
+hipError_t launch_dirichlet_mx(const DirArgs<float> &a, const StepConsts<float> &fx, const unsigned char *set, int K,
+                               int fk, int n_cu, int bpc, hipStream_t st)
 {
     if (K < 1 || K > MX_MAX_K_DISK || (fk != 0 && fk != 1)) return hipErrorInvalidValue;
     return dispatch_mx(K, [&](auto kc) -> hipError_t {
@@ -655,7 +684,7 @@ hipError_t launch_dirichlet_mx(const DirArgs<float> &a, const unsigned char *set
         if constexpr (KK > MX_MAX_K_DISK) {
             return hipErrorInvalidValue;
         } else {
-            void (*kern)(const DirArgs<float>, const unsigned char *) =
+            void (*kern)(const DirArgs<float>, const StepConsts<float>, const unsigned char *) =
                 fk == 0 ? k_dirichlet_mx<KK, 0> : k_dirichlet_mx<KK, 1>;
             int per_cu = 0;
             hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
@@ -667,7 +696,7 @@ hipError_t launch_dirichlet_mx(const DirArgs<float> &a, const unsigned char *set
             const int64_t need = (a.total + 255) / 256;
             if (blocks > need) blocks = need;
             if (blocks < 1) blocks = 1;
-            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, st, a, set);
+            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, st, a, fx, set);
             return hipGetLastError();
         }
     });

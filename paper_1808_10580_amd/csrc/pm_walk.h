@@ -26,13 +26,15 @@ __device__ __forceinline__ double source_at(const FieldArg &f, double x, double 
 // The walk itself: every lane of the block runs it; velocity(x, y, vx, vy)
 // is called by all lanes of a wave together at every step (lanes without a
 // particle pass their last position), so it may use cross-lane operations.
-template <typename T, int FK, int DOM, typename Vel>
-__device__ __forceinline__ void dirichlet_walk(const DirArgs<T> &a, Vel &&velocity)
+// C is the particle coordinate (set, at, value, advance, save, load) and sc
+// the step constants in its units.
+template <typename T, int FK, int DOM, typename C, typename Vel>
+__device__ __forceinline__ void dirichlet_walk(const DirArgs<T> &a, const StepConsts<T> &sc, Vel &&velocity)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     bool has = false, done = false;
-    Coord<T> x, y;
+    C x, y;
     x.set(0.0);
     y.set(0.0);
     double I = 0.0;
@@ -59,9 +61,9 @@ __device__ __forceinline__ void dirichlet_walk(const DirArgs<T> &a, Vel &&veloci
     auto substep = [&](T z0, T z1) {
         T vx, vy;
         velocity(x.at(), y.at(), vx, vy);
-        Coord<T> nx = x, ny = y;
-        nx.advance(vx + a.v0x, z0, a.sc);
-        ny.advance(vy + a.v0y, z1, a.sc);
+        C nx = x, ny = y;
+        nx.advance(vx + a.v0x, z0, sc);
+        ny.advance(vy + a.v0y, z1, sc);
         if (has) {
             if constexpr (FK == 2) {  // left point, one integral per Gaussian source
                 const double xd = x.value(), yd = y.value();
@@ -77,14 +79,15 @@ __device__ __forceinline__ void dirichlet_walk(const DirArgs<T> &a, Vel &&veloci
             }
             n += 1;
             // The exit test is decided in FP64.  FP32 particles first try the
-            // high words: inside by more than 2^-18 (far above the 2^-21 that
-            // the low words and FP32 rounding can move the test), the FP64
-            // test would say inside too, so it is skipped.
+            // FP32 position: inside by more than 2^-18 (far above the 2^-21
+            // that the dropped low part and FP32 rounding can move the test),
+            // the FP64 test would say inside too, so it is skipped.
             bool check = true;
             if constexpr (std::is_same<T, float>::value) {
                 constexpr float m = 0x1p-18f;
-                if constexpr (DOM == PM_DISK) check = !(__builtin_fmaf(nx.hi, nx.hi, ny.hi * ny.hi) < 1.f - m);
-                else check = !(nx.hi > m && nx.hi < 1.f - m && ny.hi > m && ny.hi < 1.f - m);
+                const float hx = nx.at(), hy = ny.at();
+                if constexpr (DOM == PM_DISK) check = !(__builtin_fmaf(hx, hx, hy * hy) < 1.f - m);
+                else check = !(hx > m && hx < 1.f - m && hy > m && hy < 1.f - m);
             }
             bool out = false;
             double nxd = 0.0, nyd = 0.0;
