@@ -241,7 +241,9 @@ int pm_jacobian_time(pm_ctx *ctx, const pm_problem *p, const double *u, const do
 
 /* One Euler-Maruyama step per entry (eq. euler), for replaying or checking
  * paths: Y[e] = step n[e] of particle (i[e], j[e]) applied to X[e], in the
- * problem's precision (X is rounded to it first).  Device arrays:
+ * problem's precision (X is rounded to it first; on the FP32 disk with the
+ * matrix-core engine to its 2^-30 fixed-point grid, for |x|, |y| < 1.5).
+ * Device arrays:
  *   X, Y [count][2] FP64, n [count] uint64, i, j [count] uint32. */
 int pm_step(pm_ctx *ctx, const pm_problem *p, const double *u, int64_t count, const double *X,
             const uint64_t *n, const uint32_t *i, const uint32_t *j, double kappa, double dt,
@@ -290,7 +292,8 @@ int pm_set_tuning(pm_ctx *ctx, int particles_per_lane, int coef_source);
  * The matrix-core kernels keep particle coordinates as 32-bit fixed-point
  * numbers: on the torus fractions of the period (resolution 2^-32, the wrap
  * by modular overflow), on the disk multiples of 2^-30 with each step's
- * increment clamped to 1/2 per axis.  They apply when sqrt(2 kappa dt) <=
+ * increment clamped to 1/2 per axis (pm_step on the disk then takes points
+ * with |x|, |y| < 1.5, as every walker is; pm_velocity any finite point).  They apply when sqrt(2 kappa dt) <=
  * 0.05; larger steps run on the vector units.  The two engines round differently, so their results agree
  * to that contract, not bit for bit; each is deterministic.  FP64 problems,
  * the square and larger K ignore the setting.  Returns PM_EINVAL for another

@@ -584,11 +584,14 @@ __global__ __launch_bounds__(256) void k_step_mx_disk(const MxStepArgs a)
     h16x8 ahi, alo;
     float inv;
     load_set(a.set, lane, ahi, alo, inv);
+    // velocity mode evaluates at the FP32 value of any finite point; step
+    // mode at the walk's fixed-point value (inside +-1.5, as for a walker)
+    const double xd = act ? a.X[2 * e] : 0.0, yd = act ? a.X[2 * e + 1] : 0.0;
     DiskFix x, y;
-    x.set(act ? a.X[2 * e] : 0.0);
-    y.set(act ? a.X[2 * e + 1] : 0.0);
+    x.set(a.V ? 0.0 : xd);
+    y.set(a.V ? 0.0 : yd);
     float vx, vy;
-    mx_velocity_disk<K>(ahi, alo, inv, x.at(), y.at(), vx, vy);
+    mx_velocity_disk<K>(ahi, alo, inv, a.V ? (float)xd : x.at(), a.V ? (float)yd : y.at(), vx, vy);
     if (!act) return;
     if (a.V) {
         a.V[2 * e] = (double)(vx + a.v0x);
