@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpm.so")
-SOURCES = ["pm_kernels.hip", "pm_abi.hip", "pm_mlp.hip", "pm_hk.hip", "pm_mx.hip", "pm_graph.hip"]
+SOURCES = ["pm_kernels.hip", "pm_abi.hip", "pm_mlp.hip", "pm_hk.hip", "pm_mx.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
