@@ -9,6 +9,10 @@
 and the chain rule for every parameter gradient.  Parameters are one flat
 vector in the order W_1, b_1, ..., W_{L+1}, b_{L+1} (row-major W: input index
 by output index).
+
+The optimiser is Adam (Kingma and Ba, "Adam: A Method for Stochastic
+Optimization", ICLR 2015, Algorithm 1) with bias-corrected first and second
+moment estimates, element by element.
 """
 from __future__ import annotations
 
@@ -101,3 +105,23 @@ def init_params(dims, seed):
         parts.append(rng.standard_normal(K * N) / np.sqrt(K))
         parts.append(np.zeros(N))
     return np.concatenate(parts)
+
+
+def adam_update(params, grad, m1, m2, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (Kingma and Ba 2015, Algorithm 1), FP64, element-wise.
+
+    step is the 1-based index t of this update; m1, m2 are the moment
+    estimates after step t - 1 (zeros before the first step).  Returns the new
+    (params, m1, m2):
+        m1 <- beta1 m1 + (1 - beta1) g
+        m2 <- beta2 m2 + (1 - beta2) g^2
+        m1_hat = m1 / (1 - beta1^t),  m2_hat = m2 / (1 - beta2^t)
+        params <- params - lr m1_hat / (sqrt(m2_hat) + eps)
+    """
+    g = np.asarray(grad, dtype=np.float64)
+    m1 = beta1 * np.asarray(m1, dtype=np.float64) + (1.0 - beta1) * g
+    m2 = beta2 * np.asarray(m2, dtype=np.float64) + (1.0 - beta2) * g * g
+    m1_hat = m1 / (1.0 - beta1 ** step)
+    m2_hat = m2 / (1.0 - beta2 ** step)
+    new = np.asarray(params, dtype=np.float64) - lr * m1_hat / (np.sqrt(m2_hat) + eps)
+    return new, m1, m2

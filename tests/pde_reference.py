@@ -70,3 +70,48 @@ def evaluate(h, k, pts):
         ey = np.exp(2j * np.pi * k * py)
         out.append(np.real(ex @ c @ ey))
     return np.array(out)
+
+
+# ---------------------------------------------------------------------------
+# Elliptic problems on a square (Theorem 3.2 with v = 0): double sine series.
+# ---------------------------------------------------------------------------
+
+def sine_coeffs(h, a, b, nmax, nq=600):
+    """c_m = (2/L) int_a^b h(s) sin(m pi (s - a) / L) ds, m = 1..nmax
+    (Gauss-Legendre quadrature, L = b - a)."""
+    L = b - a
+    t, w = np.polynomial.legendre.leggauss(nq)
+    s = a + (t + 1.0) * L / 2.0
+    w = w * L / 2.0
+    m = np.arange(1, nmax + 1)
+    S = np.sin(np.outer(m, np.pi * (s - a) / L))
+    return (2.0 / L) * (S * (w * h(s))).sum(axis=1)
+
+
+def poisson_square_separable(hx, hy, amp, kappa, x, y, d=0.0, nmax=200):
+    """theta with kappa Lap theta = amp hx(x) hy(y) on [-d, 1+d]^2 and theta = 0
+    on its boundary.  Each sine mode sin(m pi (x+d)/L) sin(n pi (y+d)/L) is an
+    eigenfunction of the Laplacian with eigenvalue -(pi/L)^2 (m^2 + n^2), so
+    theta_mn = -amp hx_m hy_n / (kappa (pi/L)^2 (m^2 + n^2))."""
+    a, b = -d, 1.0 + d
+    L = b - a
+    cx = sine_coeffs(hx, a, b, nmax)
+    cy = sine_coeffs(hy, a, b, nmax)
+    m = np.arange(1, nmax + 1)
+    lam = (np.pi / L) ** 2 * (m[:, None] ** 2 + m[None, :] ** 2)
+    C = -amp * np.outer(cx, cy) / (kappa * lam)
+    sx = np.sin(m * np.pi * (x - a) / L)
+    sy = np.sin(m * np.pi * (y - a) / L)
+    return float(sx @ C @ sy)
+
+
+def laplace_square_cos_axes(x, y, A, w, nmax=200):
+    """Harmonic theta on the unit square with theta = A (cos(w x) + cos(w y))
+    on its boundary.  g = A (cos w x + cos w y) itself satisfies Lap g = -w^2 g,
+    so theta = g + r with Lap r = w^2 g and r = 0 on the boundary, a Poisson
+    problem with two separable sources."""
+    one = lambda s: np.ones_like(s)
+    cosw = lambda s: np.cos(w * s)
+    r = (poisson_square_separable(cosw, one, A * w * w, 1.0, x, y, 0.0, nmax)
+         + poisson_square_separable(one, cosw, A * w * w, 1.0, x, y, 0.0, nmax))
+    return A * (math.cos(w * x) + math.cos(w * y)) + r

@@ -3,6 +3,24 @@
 GELU is checked against x * Phi(x) from scipy's normal CDF and its derivative
 against finite differences; the full backward pass against central finite
 differences of the loss on a small network (relative 1e-7).
+
+Adam (Kingma and Ba 2015) is pinned by what its definition fixes without
+re-deriving its update:
+  A1  a constant gradient g gives bias-corrected moments equal to g and g^2 at
+      every step, so each step moves a weight by exactly lr g / (|g| + eps)
+      (a missing or wrong bias correction moves it by another amount);
+  A2  zero gradients never move a weight; the moments of other weights do not
+      leak into it (each coordinate is its own optimiser);
+  A3  eps enters outside the square root: a gradient of 1e-10 moves a weight
+      by lr / 101 on the first step (eps inside the root would give 0.0099);
+  A4  rescaling the loss by c > 0 leaves the steps unchanged (eps aside);
+  A5  a single gradient spike after t - 1 zero gradients moves the weight by
+      lr (1 - beta1) sqrt(1 - beta2^t) / ((1 - beta1^t) sqrt(1 - beta2)),
+      (lr itself at t = 1), never more than the bound lr (1 - beta1) /
+      sqrt(1 - beta2) of the paper's Section 2.1, which it approaches as t
+      grows;
+  A6  on a quadratic the first step is lr sign(g) and Adam drives the weight
+      to the minimum.
 """
 import numpy as np
 from scipy.stats import norm
@@ -41,3 +59,70 @@ def test_backward_matches_finite_differences():
 def test_parameter_count_of_the_surrogate():
     # 168 -> 512 -> 512 -> 512 -> 49
     assert mlp.n_params(168, 512, 3, 49) == 636977
+
+
+def _run_adam(grad_fn, p0, steps, lr):
+    p, m1, m2 = np.array(p0, dtype=np.float64), np.zeros(len(p0)), np.zeros(len(p0))
+    path = [p.copy()]
+    for t in range(1, steps + 1):
+        p, m1, m2 = mlp.adam_update(p, grad_fn(p, t), m1, m2, t, lr)
+        path.append(p.copy())
+    return np.array(path)
+
+
+def test_A1_constant_gradient_steps_are_exact():
+    g = np.array([0.3, -2.0, 5e-3, 7.0])
+    lr = 1e-3
+    path = _run_adam(lambda p, t: g, np.zeros(4), 50, lr)
+    step = lr * g / (np.abs(g) + 1e-8)
+    for t in range(1, 51):
+        assert np.allclose(path[t] - path[t - 1], -step, rtol=1e-12, atol=0)
+
+
+def test_A2_zero_gradient_and_independent_coordinates():
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((20, 3))
+    G[:, 1] = 0.0
+    full = _run_adam(lambda p, t: G[t - 1], np.ones(3), 20, 1e-2)
+    assert np.all(full[:, 1] == 1.0)
+    # coordinate 0 alone follows the same path as inside the vector
+    alone = _run_adam(lambda p, t: G[t - 1, :1], np.ones(1), 20, 1e-2)
+    assert np.array_equal(alone[:, 0], full[:, 0])
+
+
+def test_A3_eps_outside_the_square_root():
+    p, _, _ = mlp.adam_update(np.zeros(1), np.array([1e-10]), np.zeros(1), np.zeros(1), 1, 1.0)
+    assert abs(-p[0] - 1.0 / 101.0) < 1e-12
+
+
+def test_A4_loss_scale_invariance():
+    rng = np.random.default_rng(4)
+    G = rng.standard_normal((30, 5))
+    a = _run_adam(lambda p, t: G[t - 1], np.zeros(5), 30, 1e-3)
+    b = _run_adam(lambda p, t: 1e3 * G[t - 1], np.zeros(5), 30, 1e-3)
+    assert np.allclose(a, b, rtol=0, atol=1e-9)
+
+
+def test_A5_sparse_spike_approaches_the_step_bound():
+    lr, b1, b2 = 1.0, 0.9, 0.999
+    bound = lr * (1 - b1) / np.sqrt(1 - b2)
+    step = 0.0
+    for t in (1, 10, 100, 1000, 10000):
+        seq = np.zeros(t)
+        seq[-1] = 2.5e4  # eps negligible
+        path = _run_adam(lambda p, s: np.array([seq[s - 1]]), np.zeros(1), t, lr)
+        step = -(path[-1, 0] - path[-2, 0])
+        expect = lr * (1 - b1) * np.sqrt(1 - b2 ** t) / ((1 - b1 ** t) * np.sqrt(1 - b2))
+        assert abs(step - expect) < 1e-9 * expect
+        assert step <= bound * (1 + 1e-12)
+        if t == 1:
+            assert abs(step - lr) < 1e-9
+    assert step > 0.99 * bound
+
+
+def test_A6_quadratic():
+    h = np.array([2.0, 0.5, 10.0])
+    p0 = np.array([1.0, -3.0, 0.2])
+    path = _run_adam(lambda p, t: h * p, p0, 4000, 1e-2)
+    assert np.allclose(path[1] - p0, -1e-2 * np.sign(h * p0), rtol=1e-6)
+    assert np.all(np.abs(path[-1]) < 2e-2)

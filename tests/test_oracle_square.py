@@ -7,7 +7,17 @@ affine source decomposition used for the optimal-forcing example.
   S3  v = 0, f = -1, g = 0: theta = E tau = sum over odd m, n of
       16 / (pi^4 kappa m n (m^2 + n^2)) sin(m pi x) sin(n pi y);
   S4  G(F) = a - B F holds exactly on common random numbers: a run with the
-      combined source equals the decomposition to rounding.
+      combined source equals the decomposition to rounding;
+  S5  v = 0, g = 0, f = A exp(-w |x - c|^2) (the Gaussian field kind of the
+      optimal-forcing example's sources): theta solves kappa Lap theta = f
+      with theta = 0 on the boundary, a double sine series whose coefficients
+      come from one-dimensional quadratures (the source is separable);
+  S6  v = 0, f = 0, g = (cos(pi x / 2) + cos(pi y / 2)) / 2 (the example's
+      boundary data, the cosine field kind): theta is the harmonic extension,
+      g plus a sine series.
+S5 and S6 also check that the tolerance would reject the plausible misreadings
+of the two field kinds (the exponent exp(-|x-c|^2 / (2 w)), swapped centre
+coordinates, the cosine scale pi x instead of pi x / 2).
 Discrete monitoring overshoots the boundary by O(sqrt(dt)); S1 and S2 carry
 an allowance of that size, S3 uses the square enlarged by the continuity
 correction 0.5826 sqrt(2 kappa dt) on each side (Broadie, Glasserman, Kou).
@@ -17,6 +27,7 @@ import math
 import numpy as np
 
 import workloads as W
+from tests.pde_reference import laplace_square_cos_axes, poisson_square_separable
 
 BETA_BGK = 0.5826
 NONE = np.zeros((0, 2), dtype=np.int32)
@@ -88,3 +99,46 @@ def test_S4_affine_source_decomposition(orc):
     r = _run(orc, f, wl.g, wl.obs, wl.kappa, wl.dt, 500, wl.seed, v0=wl.v0)
     assert np.max(np.abs(r["mean"] - (a - B @ F))) <= 1e-12
     assert np.all(B > 0)  # positive sources, positive integrals
+
+
+def _gauss_ref(cx, cy, w, A, kappa, obs, d):
+    hx = lambda s: np.exp(-w * (s - cx) ** 2)
+    hy = lambda s: np.exp(-w * (s - cy) ** 2)
+    return np.array([poisson_square_separable(hx, hy, A, kappa, x, y, d) for x, y in obs])
+
+
+def test_S5_gaussian_source_field(orc):
+    kappa, dt, Np = 0.1, 1e-4, 16000
+    obs = np.array([[0.4, 0.55], [0.2, 0.3], [0.75, 0.8]])
+    d = BETA_BGK * math.sqrt(2 * kappa * dt)  # continuity-corrected square, as in S3
+    for (cx, cy, w, A, seed) in [(0.4, 0.55, 4.0, 1.5, 21), (0.6, 0.35, 30.0, 2.0, 22)]:
+        r = _run(orc, W.fld("gauss", [cx, cy, w, A]), ZERO, obs, kappa, dt, Np, seed)
+        ref = _gauss_ref(cx, cy, w, A, kappa, obs, d)
+        se = np.sqrt(r["var"] / Np)
+        tol = 4.5 * se + 0.01 * np.abs(ref)
+        assert np.all(np.abs(r["mean"] - ref) <= tol), (w, r["mean"], ref, tol)
+        assert np.all(r["n_capped"] == 0)
+        # power: each misreading moves some observation by more than twice the tolerance
+        for wrong in (_gauss_ref(cx, cy, 1.0 / (2.0 * w), A, kappa, obs, d),   # exp(-r^2 / (2 w))
+                      _gauss_ref(cy, cx, w, A, kappa, obs, d),                # centre swapped
+                      -ref):                                                   # source sign
+            assert np.max(np.abs(wrong - ref) / tol) > 2.0
+
+
+def test_S6_cosine_boundary_data_field(orc):
+    kappa, dt, Np = 0.1, 1e-4, 16000
+    obs = np.array([[0.4, 0.55], [0.2, 0.3], [0.75, 0.8]])
+    A, w = 0.5, math.pi / 2
+    r = _run(orc, ZERO, W.fld("cos_axes", [A, w]), obs, kappa, dt, Np, 23)
+    ref = np.array([laplace_square_cos_axes(x, y, A, w) for x, y in obs])
+    # the series meets the boundary data (away from the corners)
+    for (x, y) in [(1e-9, 0.3), (0.6, 1.0 - 1e-9)]:
+        assert abs(laplace_square_cos_axes(x, y, A, w) - A * (math.cos(w * x) + math.cos(w * y))) < 2e-3
+    grad = A * w * math.sqrt(2.0)  # max |grad g| on the square
+    allow = 2 * grad * BETA_BGK * math.sqrt(2 * kappa * dt)
+    se = np.sqrt(r["var"] / Np)
+    tol = 4.5 * se + allow
+    assert np.all(np.abs(r["mean"] - ref) <= tol), (r["mean"], ref, tol)
+    for wrong in (np.array([laplace_square_cos_axes(x, y, A, 2 * w) for x, y in obs]),   # cos(pi x)
+                  np.array([laplace_square_cos_axes(x, y, 2 * A, w) for x, y in obs])):  # amplitude 1
+        assert np.max(np.abs(wrong - ref) / tol) > 2.0
