@@ -151,6 +151,32 @@ int pm_observe_time(pm_ctx *ctx, const pm_problem *p, const double *u, const dou
                     int n_obs, double kappa, double T, double dt, int64_t n_particles,
                     uint64_t seed, double *mean, double *var, double *endpoints);
 
+/* pm_observe_time without device allocation.  For callers that cannot
+ * allocate device memory at call time: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Arguments, results
+ * (bitwise those of pm_observe_time: the same kernels, launch sequence and
+ * Philox streams), errors and stream semantics are those of pm_observe_time.
+ * The call itself calls no hipMalloc, hipFree or other allocating routine:
+ * its per-call device buffers (folded coefficients, matrix-core operands,
+ * per-chunk partial statistics, final particle states) are carved from one
+ * fixed array of PM_NOALLOC_SCRATCH_MIB MiB of device memory that the
+ * library holds on each GPU it runs on, from the first pm_create on that GPU
+ * until the process ends (the context's own queue counter and error flags,
+ * made by pm_create, are used as usual).
+ * Limit: n_obs * ceil(n_particles / 64) <= PM_NOALLOC_MAX_CHUNKS (81,920
+ * chunks: 5.24e6 particles, e.g. 49 points x 1e5 particles); larger requests
+ * return PM_EINVAL before any launch.
+ * Sharing: every call on one GPU uses that GPU's one array, whatever its
+ * context.  Calls that overlap in time on one GPU (different streams, host
+ * threads or contexts) race and give undefined results; calls ordered on one
+ * stream, or separated by pm_sync, are safe.  The array keeps the last call's
+ * contents; each call writes every value it reads from it before reading. */
+#define PM_NOALLOC_MAX_CHUNKS 81920
+#define PM_NOALLOC_SCRATCH_MIB 83
+int pm_observe_time_noalloc(pm_ctx *ctx, const pm_problem *p, const double *u, const double *obs_pts,
+                            int n_obs, double kappa, double T, double dt, int64_t n_particles,
+                            uint64_t seed, double *mean, double *var, double *endpoints);
+
 /* Gaussian sources with unknown weights (the optimal-forcing example of
  * Section 4): for f = sum_q f_q phi_q, phi_q(x) = exp(-w_q |x - c_q|^2),
  * Theorem 3.2 gives theta(x_i) = a_i - sum_q B_qi f_q with

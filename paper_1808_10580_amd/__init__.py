@@ -27,6 +27,7 @@ FP32, FP64 = 0, 1
 FIELD_KINDS = {"zero": 0, "const": 1, "sinsin": 2, "fourier": 3, "gauss_periodic": 4,
                "cos_m_theta": 5, "exp_linear": 6, "linear": 7, "gauss": 8, "cos_axes": 9}
 MAX_SOURCES = 4
+NOALLOC_MAX_CHUNKS = 81920  # pm_observe_time_noalloc: n_obs * ceil(Np / 64) at most
 MAX_K = 8
 MAX_K_MX = 8  # FP32 torus problems with 1 <= K <= MAX_K_MX use the matrix cores by default
 MAX_K_DISK_MX = 4  # the same for FP32 disk problems
@@ -83,6 +84,7 @@ def _declare(L):
     L.pm_problem_destroy.argtypes = [_vp]
     L.pm_problem_destroy.restype = None
     L.pm_observe_time.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _d, _i64, _u64, _vp, _vp, _vp]
+    L.pm_observe_time_noalloc.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _d, _i64, _u64, _vp, _vp, _vp]
     L.pm_observe_time_multi.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp, C.c_int, _d, _d, _i64, _u64,
                                         _vp, _vp]
     L.pm_jacobian_time.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _d, _i64, _u64, _d, _vp]
@@ -298,6 +300,28 @@ class Problem:
                                     float(dt), int(n_particles), int(seed), _ptr(mean), _ptr(var), _ptr(ep))
         _check(st, "pm_observe_time")
         return (mean, var, ep) if endpoints else (mean, var)
+
+    def observe_time_noalloc(self, u, obs, kappa, T, dt, n_particles, seed, mean, var, endpoints=None):
+        """pm_observe_time_noalloc: Algorithm 1 into caller-provided CUDA float64
+        tensors mean, var ([n_obs]) and optional endpoints ([n_obs][Np][2]);
+        the library allocates no device memory during the call."""
+        torch = _torch()
+        self.ctx.bind_stream()
+        ut = self._u(u)
+        ob = _dev(obs, torch.float64, self.ctx.device).reshape(-1, 2)
+        n_obs = ob.shape[0]
+        for name, t, shape in (("mean", mean, (n_obs,)), ("var", var, (n_obs,)),
+                               ("endpoints", endpoints, (n_obs, int(n_particles), 2))):
+            if t is None and name == "endpoints":
+                continue
+            if (t is None or t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape
+                    or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous CUDA float64 tensor of shape {shape}")
+        st = _lib().pm_observe_time_noalloc(self.ctx.h, self.h, _ptr(ut), _ptr(ob), n_obs, float(kappa), float(T),
+                                            float(dt), int(n_particles), int(seed), _ptr(mean), _ptr(var),
+                                            _ptr(endpoints))
+        _check(st, "pm_observe_time_noalloc")
+        return mean, var
 
     def observe_time_multi(self, u, obs, kappa, read_steps: Sequence[int], dt, n_particles, seed):
         """Observations at t_k = read_steps[k] * dt along one ensemble per point:

@@ -8,12 +8,59 @@
 #include <cstdint>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "pm_mx.h"
 
 using namespace pm;
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of pm_observe_time_noalloc: one copy of this array per GPU
+// (the code object's device memory), held until the process ends.  Regions,
+// each 256-byte aligned: folded coefficients (the largest is the high-K
+// matrix-core block of |k| <= PM_MAX_K_MFMA), matrix-core operands of the
+// small-K engine, chunk partials [chunks][3] FP64, final states
+// [chunks][64][2] FP64.  Host code reaches it only through the address
+// hipGetSymbolAddress returns per device (noalloc_scratch).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t NA_COEF_BYTES = (size_t)512 << 10;
+constexpr size_t NA_MX_BYTES = (size_t)4 << 10;
+constexpr size_t NA_PART_BYTES = (size_t)PM_NOALLOC_MAX_CHUNKS * 3 * sizeof(double);
+constexpr size_t NA_STATE_BYTES = (size_t)PM_NOALLOC_MAX_CHUNKS * 64 * 2 * sizeof(double);
+constexpr size_t NA_BYTES = NA_COEF_BYTES + NA_MX_BYTES + NA_PART_BYTES + NA_STATE_BYTES;
+static_assert(NA_PART_BYTES % 256 == 0 && NA_STATE_BYTES % 256 == 0, "region alignment");
+static_assert(NA_BYTES <= ((size_t)PM_NOALLOC_SCRATCH_MIB << 20), "stated scratch size");
+constexpr int NA_MAX_DEVICES = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NA_MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+// Looked up once per device (pm_create); later calls return the kept value.
+int noalloc_scratch(int device, void **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= NA_MAX_DEVICES) return PM_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return PM_EDEVICE;
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return PM_OK;
+}
+}  // namespace
 
 struct pm_ctx {
     int device = 0;
@@ -77,6 +124,10 @@ struct pm_ctx {
     int tune_ppl[PM_MAX_K + 1] = {0};  // autotuned choice per harmonic count K
     int tune_src[PM_MAX_K + 1] = {0};
     bool capturing = false;  // recording a graph: no timing events, no host waits
+    // pm_observe_time_noalloc: the per-call buffers point into the fixed
+    // scratch for the duration of the call, and ensure() may not allocate
+    bool no_alloc = false;
+    void *scratch = nullptr;  // this device's fixed scratch (noalloc_scratch)
     // Lifetime: the caller's handle plus one reference per live problem.
     // pm_destroy releases the device resources at once; the struct itself is
     // freed with the last reference, so problems may be destroyed after it.
@@ -122,6 +173,7 @@ int ensure(pm_ctx *c, void **ptr, size_t *cap, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
     if (*cap >= bytes) return PM_OK;
+    if (c->no_alloc) return PM_EINVAL;  // a fixed-scratch region is too small: never allocate
     if (*ptr) {
         if (hipStreamSynchronize(c->stream) != hipSuccess) return PM_EDEVICE;
         (void)hipFree(*ptr);
@@ -787,6 +839,11 @@ int pm_create(pm_ctx **out, int device, void *stream)
         return PM_EDEVICE;
     }
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    const int sst = noalloc_scratch(device, &c->scratch);
+    if (sst != PM_OK && sst != PM_EUNSUPPORTED) {
+        delete c;
+        return sst;
+    }
     if (hipMalloc((void **)&c->d_flags, 64) != hipSuccess ||
         hipMalloc((void **)&c->d_queue, 64) != hipSuccess ||
         hipMemset(c->d_flags, 0, 64) != hipSuccess ||
@@ -966,6 +1023,56 @@ int pm_observe_time(pm_ctx *c, const pm_problem *p, const double *u, const doubl
     if (p->prec == PM_FP64)
         return observe_time_impl<double>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, T, dt, mean, var, endpoints);
     return observe_time_impl<float>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, T, dt, mean, var, endpoints);
+}
+
+int pm_observe_time_noalloc(pm_ctx *c, const pm_problem *p, const double *u, const double *obs, int n_obs,
+                            double kappa, double T, double dt, int64_t np, uint64_t seed, double *mean,
+                            double *var, double *endpoints)
+{
+    if (!ctx_ok(c, p)) return PM_EINVAL;
+    if (p->domain != PM_TORUS || !p->has_theta0) return PM_EINVAL;
+    if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(obs) || bad_ptr(mean) || bad_ptr(var)) return PM_EINVAL;
+    if (n_obs < 1) return PM_EINVAL;
+    if (np < 1 || np > ((int64_t)1 << 32)) return PM_EINVAL;
+    if (check_time_args(kappa, T, dt)) return PM_EINVAL;
+    if ((np + 63) / 64 > PM_NOALLOC_MAX_CHUNKS / n_obs) return PM_EINVAL;
+    if (!c->scratch) return PM_EUNSUPPORTED;  // device index beyond the scratch table
+    // coefficient bytes of this problem: FP64 fold (also the small-K
+    // matrix-core engine's first stage), or the high-K matrix-core block
+    const int B = 2 * p->K + 1;
+    const size_t coef_bytes = p->hk ? (size_t)hk_set_bytes(p->K)
+                                    : (size_t)B * row_stride(p->domain, p->K) * sizeof(double);
+    if (coef_bytes > NA_COEF_BYTES || (size_t)MX_SET_BYTES > NA_MX_BYTES) return PM_EUNSUPPORTED;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+
+    // point the per-call buffers at the scratch for this call only
+    unsigned char *base = static_cast<unsigned char *>(c->scratch);
+    void *save_ptr[4] = {c->coef, c->mx, c->part, c->states};
+    const size_t save_cap[4] = {c->coef_cap, c->mx_cap, c->part_cap, c->states_cap};
+    c->coef = base;
+    c->coef_cap = NA_COEF_BYTES;
+    c->mx = base + NA_COEF_BYTES;
+    c->mx_cap = NA_MX_BYTES;
+    c->part = base + NA_COEF_BYTES + NA_MX_BYTES;
+    c->part_cap = NA_PART_BYTES;
+    c->states = base + NA_COEF_BYTES + NA_MX_BYTES + NA_PART_BYTES;
+    c->states_cap = NA_STATE_BYTES;
+    c->no_alloc = true;
+    const int st = p->prec == PM_FP64
+                       ? observe_time_impl<double>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, T, dt, mean, var,
+                                                   endpoints)
+                       : observe_time_impl<float>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, T, dt, mean, var,
+                                                  endpoints);
+    c->no_alloc = false;
+    c->coef = save_ptr[0];
+    c->mx = save_ptr[1];
+    c->part = save_ptr[2];
+    c->states = save_ptr[3];
+    c->coef_cap = save_cap[0];
+    c->mx_cap = save_cap[1];
+    c->part_cap = save_cap[2];
+    c->states_cap = save_cap[3];
+    return st;
 }
 
 int pm_observe_time_multi(pm_ctx *c, const pm_problem *p, const double *u, const double *obs, int n_obs,

@@ -60,3 +60,14 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(pm, "_LIBH", None)
     with pytest.raises(RuntimeError, match="not built"):
         pm.lib()
+
+
+def test_noalloc_limit_matches_the_header_and_null_arguments_are_rejected(lib):
+    import paper_1808_10580_amd as pm
+    txt = open(HEADER).read()
+    m = re.search(r"#define PM_NOALLOC_MAX_CHUNKS (\d+)", txt)
+    assert m and int(m.group(1)) == pm.NOALLOC_MAX_CHUNKS
+    f = lib.pm_observe_time_noalloc
+    f.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int] + [ctypes.c_double] * 3 + \
+        [ctypes.c_int64, ctypes.c_uint64] + [ctypes.c_void_p] * 3
+    assert f(None, None, None, None, 1, 0.1, 1.0, 0.1, 1, 0, None, None, None) == -1
