@@ -232,7 +232,9 @@ int pm_observe_time_multi(pm_ctx *ctx, const pm_problem *p, const double *u, con
  *   tau_mean, tau_var device [n_obs] exit-time statistics (time units)
  *   n_capped  device [n_obs] int64
  *   paths     device [n_obs][n_particles][4] FP64 (exit x, exit y, payoff,
- *             exit step) per path, or NULL */
+ *             exit step) per path, or NULL
+ * On the disk with FP32 and the matrix-core engine the observation points
+ * must have |x|, |y| < 1.5 (see pm_sync). */
 int pm_observe_dirichlet(pm_ctx *ctx, const pm_problem *p, const double *u, const pm_field *f,
                          const pm_field *g, const double *obs_pts, int n_obs, double kappa,
                          double dt, int64_t n_particles, uint64_t seed, int64_t max_steps,
@@ -268,7 +270,8 @@ int pm_jacobian_time(pm_ctx *ctx, const pm_problem *p, const double *u, const do
 /* One Euler-Maruyama step per entry (eq. euler), for replaying or checking
  * paths: Y[e] = step n[e] of particle (i[e], j[e]) applied to X[e], in the
  * problem's precision (X is rounded to it first; on the FP32 disk with the
- * matrix-core engine to its 2^-30 fixed-point grid, for |x|, |y| < 1.5).
+ * matrix-core engine to its 2^-30 fixed-point grid, which requires
+ * |x|, |y| < 1.5: other points are reported by pm_sync).
  * Device arrays:
  *   X, Y [count][2] FP64, n [count] uint64, i, j [count] uint32. */
 int pm_step(pm_ctx *ctx, const pm_problem *p, const double *u, int64_t count, const double *X,
@@ -286,8 +289,13 @@ int pm_normals(pm_ctx *ctx, const pm_problem *p, int64_t count, const uint64_t *
                const uint32_t *i, const uint32_t *j, uint64_t seed, double *Z);
 
 /* Wait for the context's stream.  Returns PM_EDEVICE on a runtime error,
- * else PM_ENONFINITE / PM_ECAPPED if a call since the previous pm_sync saw
- * a non-finite payoff or a capped path, else PM_OK.  Clears the flags. */
+ * else PM_EUNSUPPORTED if a call since the previous pm_sync gave an FP32 disk
+ * problem on the matrix-core engine a start point (observation point, or
+ * pm_step input) with |x| or |y| >= 1.5, which its fixed-point coordinates
+ * do not hold (that call's results are undefined; the vector engine,
+ * pm_set_velocity_engine(PM_ENGINE_VALU), takes any point), else
+ * PM_ENONFINITE / PM_ECAPPED if a call saw a non-finite payoff or a capped
+ * path, else PM_OK.  Clears the flags. */
 int pm_sync(pm_ctx *ctx);
 
 /* Time of the last kernel of the most recent observe call, measured with

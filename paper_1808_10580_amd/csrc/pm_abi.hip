@@ -594,6 +594,8 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
             ma.t = a;
             ma.fx = fixed_consts(dte, kappa);
             ma.sets = mx_sets;
+            ma.vmax_fast = (float)((0.45 - 5.9 * std::sqrt(2.0 * kappa * dte)) / dte -
+                                   std::max(std::fabs(p->v0[0]), std::fabs(p->v0[1])));
             le = launch_time_mx(ma, p->K, c->n_cu, c->bpc, c->stream);
         } else {
             le = launch_time<T>(a, p->K, ppl, src, c->n_cu, c->bpc, c->stream);
@@ -723,6 +725,7 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     a.min_iters = 1024;
 
     if (launch_zero_u64(c->d_queue, 1, c->stream) != hipSuccess) return PM_EDEVICE;
+    if (mx && launch_check_disk_range(obs, n_obs, c->d_flags, c->stream) != hipSuccess) return PM_EDEVICE;
     PM_HIP(hipEventRecord(c->ev0, c->stream));
     a.mode = 0;
     a.dump_below = n_follow > 0 ? c->dir_dump : 0;
@@ -1246,6 +1249,8 @@ static int step_mx(pm_ctx *c, const pm_problem *p, const double *u, int64_t coun
     a.v0y = (float)p->v0[1];
     a.Y = Y;
     a.V = V;
+    if (p->domain == PM_DISK && Y && launch_check_disk_range(X, count, c->d_flags, c->stream) != hipSuccess)
+        return PM_EDEVICE;
     return launch_step_mx(a, p->K, p->domain, c->stream) == hipSuccess ? PM_OK : PM_EDEVICE;
 }
 
@@ -1332,6 +1337,7 @@ int pm_sync(pm_ctx *c)
     unsigned h = 0;
     if (hipMemcpy(&h, c->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess) return PM_EDEVICE;
     if (h && hipMemset(c->d_flags, 0, sizeof(unsigned)) != hipSuccess) return PM_EDEVICE;
+    if (h & PM_FLAG_RANGE) return PM_EUNSUPPORTED;
     if (h & PM_FLAG_NONFINITE) return PM_ENONFINITE;
     if (h & PM_FLAG_CAPPED) return PM_ECAPPED;
     return PM_OK;

@@ -11,7 +11,7 @@
 
 namespace pm {
 
-enum : unsigned { PM_FLAG_NONFINITE = 1u, PM_FLAG_CAPPED = 2u };
+enum : unsigned { PM_FLAG_NONFINITE = 1u, PM_FLAG_CAPPED = 2u, PM_FLAG_RANGE = 4u };
 enum { PM_COEF_LDS = 0, PM_COEF_SCALAR = 1 };
 
 struct FoldArgs {

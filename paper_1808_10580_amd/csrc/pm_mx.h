@@ -26,7 +26,8 @@ static_assert(MX_SET_BYTES % 16 == 0, "set alignment");
 struct MxHeader {
     float inv_scale;  // 2^-(coefficient shift + MX_BASIS_SHIFT)
     float cmax;       // max |Cx|, |Cy|
-    float pad[14];
+    float vbound;     // >= max over components of sum |C_c[i][j]| >= max |v| (torus; |phi| <= 1)
+    float pad[13];
 };
 static_assert(sizeof(MxHeader) == 64, "operand alignment");
 
@@ -51,6 +52,11 @@ struct MxTimeArgs {
     TimeArgs<float> t;           // chunk layout, steps, readouts, outputs (t.coef, t.sc unused)
     StepConsts<float> fx;        // dt (hi + lo) and sqrt(2 kappa dt), each x 2^32
     const unsigned char *sets;   // [n_u][MX_SET_BYTES]
+    // A parameter set whose vbound is at most vmax_fast moves a particle by
+    // less than 0.45 of the period per step (drift plus the largest normal),
+    // so the 32-bit increment of the fixed-point update cannot overflow;
+    // other sets take the 64-bit increment (exact modulo the period).
+    float vmax_fast;
 };
 
 struct MxStepArgs {
@@ -68,6 +74,9 @@ struct MxStepArgs {
     double *V;  // velocity mode when non-null (n, i, j, Y unused)
 };
 
+// Sets PM_FLAG_RANGE in *flags unless every point of X [count][2] has
+// |x|, |y| < 1.5 (the start points the disk fixed-point coordinates hold).
+hipError_t launch_check_disk_range(const double *X, int64_t count, unsigned *flags, hipStream_t st);
 hipError_t launch_pack_mx(const MxPackArgs &a, unsigned char *out, int n_sets, hipStream_t st);
 hipError_t launch_time_mx(const MxTimeArgs &a, int K, int n_cu, int bpc, hipStream_t st);
 hipError_t launch_step_mx(const MxStepArgs &a, int K, int domain, hipStream_t st);

@@ -65,6 +65,26 @@ __global__ __launch_bounds__(256) void k_pack_mx(const MxPackArgs a, unsigned ch
         __syncthreads();
     }
     const double cmax = red[0];
+    // velocity bound: the larger of sum |Cx| and sum |Cy| over the whole
+    // matrix (every basis function is bounded by 1); torus only
+    double vb = 0.0;
+    if (nf == 2) {
+        double sx = 0.0, sy = 0.0;
+        for (int e = threadIdx.x; e < B * B; e += blockDim.x) {
+            const int j = e / B, i = e % B;
+            sx += fabs(C[j * R + 2 * i]);
+            sy += fabs(C[j * R + 2 * i + 1]);
+        }
+        __syncthreads();
+        red[threadIdx.x] = fmax(sx, sy);
+        __syncthreads();
+        // sum of the per-thread maxima >= max of the two sums
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        vb = red[0];
+    }
     int sc = 0;
     if (cmax > 0.0) {
         int ex;
@@ -78,7 +98,8 @@ __global__ __launch_bounds__(256) void k_pack_mx(const MxPackArgs a, unsigned ch
     if (threadIdx.x == 0) {
         hd->inv_scale = ldexpf(1.f, -(sc + MX_BASIS_SHIFT));
         hd->cmax = (float)cmax;
-        for (int q = 0; q < 14; ++q) hd->pad[q] = 0.f;
+        hd->vbound = (float)(vb * (1.0 + 0x1p-10));  // covers FP32 rounding of the bound and the bases
+        for (int q = 0; q < 13; ++q) hd->pad[q] = 0.f;
     }
     _Float16 *hi = reinterpret_cast<_Float16 *>(set + sizeof(MxHeader));
     _Float16 *lo = hi + 64 * 8;
@@ -359,6 +380,22 @@ struct FixCoord {
         d = __builtin_fmaf(-c.dth, vel, d);
         X += (uint32_t)(int32_t)__builtin_rintf(d);
     }
+    // The same for an increment of any size, reduced modulo the period
+    // first: with |d| held below 2^50 units, t = d 2^-32 and t + 1/2 are
+    // exact, q = floor(t + 1/2) is the nearest whole number of periods, and
+    // r = d - q 2^32 is exact (d and q 2^32 lie within a factor 2 of each
+    // other when q != 0) and in [-2^31, 2^31), an FP32 multiple of 128 units
+    // near its ends, so its rounding to a whole unit fits 32 bits.  Equal to
+    // advance whenever |d| < 2^31 - 64.
+    __device__ __forceinline__ void advance_wide(float vel, float z, const StepConsts<float> &c)
+    {
+        float d = __builtin_fmaf(-c.dtl, vel, c.sq * z);
+        d = __builtin_fmaf(-c.dth, vel, d);
+        d = __builtin_fminf(__builtin_fmaxf(d, -0x1p50f), 0x1p50f);
+        const float q = __builtin_floorf(__builtin_fmaf(d, 0x1p-32f, 0.5f));
+        const float r = __builtin_fmaf(q, -0x1p32f, d);
+        X += (uint32_t)(int32_t)__builtin_rintf(r);
+    }
 };
 
 // Disk coordinate as a signed 32-bit multiple of 2^-30 (range +-2): the
@@ -406,6 +443,11 @@ __device__ __forceinline__ void load_set(const unsigned char *__restrict__ set, 
     inv = reinterpret_cast<const MxHeader *>(set)->inv_scale;
 }
 
+__device__ __forceinline__ float set_vbound(const unsigned char *__restrict__ set)
+{
+    return reinterpret_cast<const MxHeader *>(set)->vbound;
+}
+
 // ---------------------------------------------------------------------------
 // Algorithm 1, persistent: one task is one 64-particle chunk of one parameter
 // set, one wave per task; lane l of chunk q of observation j runs particle
@@ -425,6 +467,7 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
     int cur_b = -1;
     h16x8 ahi = {}, alo = {};
     float inv = 0.f;
+    bool wide = false;
     for (;;) {
         unsigned long long tk = 0;
         if (lane == 0) tk = atomicAdd(a.queue, 1ull);
@@ -453,6 +496,7 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
         if (b != cur_b) {
             const unsigned char *set = m.sets + (int64_t)b * MX_SET_BYTES;
             load_set(set, lane, ahi, alo, inv);
+            wide = !(set_vbound(set) <= m.vmax_fast);  // wave-uniform; NaN takes the wide path
             if constexpr (K == 8) {
                 const float *src = reinterpret_cast<const float *>(set + MX_BORDER_OFFSET);
                 wave_lds_sync();
@@ -472,13 +516,6 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
         x.set(a.obs[2 * j]);
         y.set(a.obs[2 * j + 1]);
 
-        auto step = [&](float z0, float z1) {
-            float vx, vy;
-            if constexpr (K == 8) __asm__ volatile("" ::: "memory");  // re-read the borders every step
-            mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy, my_border);
-            x.advance(vx + a.v0x, z0, m.fx);
-            y.advance(vy + a.v0y, z1, m.fx);
-        };
         int r = 0;
         int64_t next = a.read_at[0];
         auto readout = [&](int64_t done) {
@@ -491,24 +528,43 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
             }
         };
         readout(0);
-        int64_t n = 0;
-        for (; n + 1 < a.n_steps; n += 2) {
-            const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi, pj, k0, k1);
-            float z0, z1, z2, z3;
-            box_muller(w.x, w.y, z0, z1);
-            box_muller(w.z, w.w, z2, z3);
-            step(z0, z1);
-            readout(n + 1);
-            step(z2, z3);
-            readout(n + 2);
-        }
-        if (n < a.n_steps) {
-            const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi, pj, k0, k1);
-            float z0, z1;
-            box_muller(w.x, w.y, z0, z1);
-            step(z0, z1);
-            readout(n + 1);
-        }
+        // the step loop, with the 32-bit or (set with a large velocity bound)
+        // the 64-bit increment
+        auto walk = [&](auto wide_c) {
+            constexpr bool WIDE = decltype(wide_c)::value;
+            auto step = [&](float z0, float z1) {
+                float vx, vy;
+                if constexpr (K == 8) __asm__ volatile("" ::: "memory");  // re-read the borders every step
+                mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy, my_border);
+                if constexpr (WIDE) {
+                    x.advance_wide(vx + a.v0x, z0, m.fx);
+                    y.advance_wide(vy + a.v0y, z1, m.fx);
+                } else {
+                    x.advance(vx + a.v0x, z0, m.fx);
+                    y.advance(vy + a.v0y, z1, m.fx);
+                }
+            };
+            int64_t n = 0;
+            for (; n + 1 < a.n_steps; n += 2) {
+                const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi, pj, k0, k1);
+                float z0, z1, z2, z3;
+                box_muller(w.x, w.y, z0, z1);
+                box_muller(w.z, w.w, z2, z3);
+                step(z0, z1);
+                readout(n + 1);
+                step(z2, z3);
+                readout(n + 2);
+            }
+            if (n < a.n_steps) {
+                const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi, pj, k0, k1);
+                float z0, z1;
+                box_muller(w.x, w.y, z0, z1);
+                step(z0, z1);
+                readout(n + 1);
+            }
+        };
+        if (wide) walk(std::true_type{});
+        else walk(std::false_type{});
         if (!MT) {
             double *S = a.states + 2 * ((cb + ch) * 64 + lane);
             S[0] = x.value();
@@ -550,8 +606,8 @@ __global__ __launch_bounds__(256) void k_step_mx(const MxStepArgs a)
     float z0, z1;
     if ((n & 1) == 0) box_muller(w.x, w.y, z0, z1);
     else box_muller(w.z, w.w, z0, z1);
-    x.advance(vx + a.v0x, z0, a.fx);
-    y.advance(vy + a.v0y, z1, a.fx);
+    x.advance_wide(vx + a.v0x, z0, a.fx);
+    y.advance_wide(vy + a.v0y, z1, a.fx);
     double nx = x.value(), ny = y.value();
     nx -= floor(nx);
     ny -= floor(ny);
@@ -609,6 +665,17 @@ __global__ __launch_bounds__(256) void k_step_mx_disk(const MxStepArgs a)
     a.Y[2 * e + 1] = y.value();
 }
 
+// Start points of the disk's fixed-point walk: a coordinate of magnitude
+// 1.5 or more (or not finite) is outside what the walk represents.
+__global__ __launch_bounds__(256) void k_check_disk_range(const double *__restrict__ X, int64_t count,
+                                                          unsigned *flags)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const double x = X[2 * e], y = X[2 * e + 1];
+    if (!(fabs(x) < 1.5 && fabs(y) < 1.5)) atomicOr(flags, PM_FLAG_RANGE);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
@@ -626,6 +693,13 @@ static hipError_t dispatch_mx(int K, F &&f)
     case 8: return f(std::integral_constant<int, 8>{});
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_check_disk_range(const double *X, int64_t count, unsigned *flags, hipStream_t st)
+{
+    if (count < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_check_disk_range, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, X, count, flags);
+    return hipGetLastError();
 }
 
 hipError_t launch_pack_mx(const MxPackArgs &a, unsigned char *out, int n_sets, hipStream_t st)

@@ -167,6 +167,40 @@ def test_teacher_forced_steps(pm, ctx, orc, engine_of, wl_name, prec, tol, engin
     assert np.max(d) <= tol
 
 
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+def test_fp32_steps_longer_than_half_the_period(pm, ctx, orc, engine_of, engine):
+    """A constant drift that carries every particle 0.70 and 1.30 periods per
+    step (the matrix-core engine's 32-bit fixed-point increment alone would
+    overflow; its parameter set then takes the exact 64-bit-range path):
+    teacher-forced steps and 20-step paths follow the oracle.  The FP32 sum
+    v + v0 and the rounding of an increment of 1.3 periods carry about 1e-7
+    per step."""
+    engine_of(engine)
+    wl = W.time_small()
+    v0 = (700.3, -1301.7)
+    T, Np = 20 * wl.dt, 256
+    prob = pm.Problem(ctx, "torus", wl.modes, v0=v0, theta0=wl.theta0, prec="fp32")
+    dte = wl.dt
+    rows = []
+    for j in range(wl.n_obs):
+        for i in range(8):
+            P = orc.path("torus", wl.modes, wl.u, wl.kappa, dte, wl.seed, i, j, wl.obs[j], 20, v0=v0)
+            rows += [(P[n], P[n + 1], n, i, j) for n in range(0, 20, 3)]
+    X, Yref = np.array([r[0] for r in rows]), np.array([r[1] for r in rows])
+    n, i, j = (np.array([r[k] for r in rows]) for k in (2, 3, 4))
+    Y = np_(prob.step(wl.u, X, n, i, j, wl.kappa, dte, wl.seed))
+    d1 = tdist(Y, Yref)
+    m, v, ep = prob.observe_time(wl.u, wl.obs, wl.kappa, T, wl.dt, Np, wl.seed, endpoints=True)
+    assert ctx.sync() == pm.PM_OK
+    _, ep_ref = orc.observe_time_payoffs(wl.modes, wl.u, wl.theta0, wl.obs, wl.kappa, T, wl.dt, Np, wl.seed,
+                                         v0=v0, endpoints=True)
+    err = np.max(tdist(np_(ep), ep_ref), axis=-1)
+    print("steps of 0.7 / 1.3 periods, %s: teacher-forced max %.2e; 20-step paths max %.2e p99 %.2e"
+          % (engine, d1.max(), err.max(), np.quantile(err, 0.99)))
+    assert d1.max() <= 1e-6
+    assert err.max() <= 1e-5
+
+
 # ---------------------------------------------------------------------------
 # P2 / P3: full paths
 # ---------------------------------------------------------------------------
