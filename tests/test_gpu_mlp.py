@@ -132,3 +132,92 @@ def test_training_fits_a_teacher_network(pm, ctx):
     ref = orc_mlp.predict(net.get_params().astype(np.float64), dims, Xv, None, mu, sd)
     assert _rel(y - mu, ref - mu) < fwd_tol(dims)
     net.close()
+
+
+def test_adam_steps_match_the_fp64_oracle_elementwise(pm, ctx):
+    """Six Adam steps (Kingma and Ba, Algorithm 1: bias-corrected moments,
+    beta = (0.9, 0.999), eps = 1e-8) on one batch from identical weights.
+
+    (a) Arithmetic.  The train step uses the gradient pm_mlp_grads returns at
+    the same weights, so at every step the GPU's new weights must equal the
+    FP64 oracle's Adam update applied to the GPU's own gradients (moments
+    carried over the same gradient sequence), element by element, to FP32
+    rounding.  The moment updates b m + (1 - b) g round relative to their
+    terms, not their (possibly cancelling) result, so the bound is 2 ulp of
+    the weight, plus lr c1 8 s 2^-24 S1 / (sqrt(v^) + eps) with S1 the same
+    exponential average of |g| as m1 (t = s steps, c1 = 1 / (1 - b1^s)),
+    plus 1e-5 of the update (division, square root, constants in FP32).
+
+    (b) Trajectory.  Against the oracle's own FP64 run (FP64 gradients at its
+    own weights), every parameter stays within the bound that the measured
+    gradient differences dg_s = g_gpu,s - g_ref,s imply for Adam:
+        |m^_gpu - m^_ref| <= sum_s w1_s |dg_s| / (1 - b1^t) = A_m,
+        |sqrt(v^_gpu) - sqrt(v^_ref)| <= (sum_s w2_s dg_s^2 / (1 - b2^t))^(1/2) = A_v
+    (the triangle inequality of the weighted 2-norm), so the update differs by
+    at most (A_m + |u_ref| A_v) / (sqrt(v^_gpu) + eps), summed over steps
+    with the learning rate; the gradient differences themselves are within
+    the BF16 bound of test_gradients_match_oracle, layer by layer."""
+    dims, n, lr, steps = FULL, 256, 1e-3, 6
+    b1, b2, eps = 0.9, 0.999, 1e-8
+    net, p, x, t, scale, mu, sd = _setup(pm, ctx, dims, n, 6)
+    p0 = net.get_params().astype(np.float64)
+    # (a) and the GPU's gradient sequence
+    m1 = np.zeros_like(p0)
+    m2 = np.zeros_like(p0)
+    S1 = np.zeros_like(p0)
+    g_gpu, p_gpu, tols = [], [p0], []
+    worst_a = 0.0
+    for s in range(1, steps + 1):
+        g = net.grads(x, t).astype(np.float64)
+        before = net.get_params().astype(np.float64)
+        net.train_step(x, t, lr)
+        after = net.get_params().astype(np.float64)
+        ref, m1, m2 = orc_mlp.adam_update(before, g, m1, m2, s, lr, b1, b2, eps)
+        S1 = b1 * S1 + (1 - b1) * np.abs(g)
+        c1 = 1.0 / (1.0 - b1 ** s)
+        vhat = m2 / (1.0 - b2 ** s)
+        tol = (2 * np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+               + lr * c1 * 8 * s * 2.0 ** -24 * S1 / (np.sqrt(vhat) + eps)
+               + 1e-5 * np.abs(ref - before) + 1e-30)
+        r = np.abs(after - ref) / tol
+        worst_a = max(worst_a, np.max(r))
+        k = int(np.argmax(r))
+        assert np.all(r <= 1), (s, k, before[k], after[k], ref[k], g[k], m1[k], m2[k], tol[k])
+        tols.append(tol)
+        g_gpu.append(g)
+        p_gpu.append(after)
+    # (b) the oracle's own FP64 run from the same start
+    pr = p0.copy()
+    r1 = np.zeros_like(pr)
+    r2 = np.zeros_like(pr)
+    bound = np.zeros_like(pr)
+    dgs = []
+    worst_g = 0.0
+    for s in range(1, steps + 1):
+        _, gr = orc_mlp.loss_and_grads(pr, dims, x, t, scale, mu, sd)
+        # the measured gradient difference is within the BF16 bound, layer by layer
+        off = 0
+        for K, N in orc_mlp.layer_dims(*dims):
+            for size in (K * N, N):
+                e = _rel(g_gpu[s - 1][off:off + size], gr[off:off + size])
+                worst_g = max(worst_g, e)
+                assert e < grad_tol(dims)
+                off += size
+        dgs.append(g_gpu[s - 1] - gr)
+        pr_new, r1, r2 = orc_mlp.adam_update(pr, gr, r1, r2, s, lr, b1, b2, eps)
+        u_ref = (pr - pr_new) / lr
+        w1 = np.array([(1 - b1) * b1 ** (s - q) for q in range(1, s + 1)])
+        w2 = np.array([(1 - b2) * b2 ** (s - q) for q in range(1, s + 1)])
+        A_m = sum(w * np.abs(dg) for w, dg in zip(w1, dgs)) / (1 - b1 ** s)
+        A_v = np.sqrt(sum(w * dg * dg for w, dg in zip(w2, dgs)) / (1 - b2 ** s))
+        v_gpu = sum(w * g * g for w, g in zip(w2, g_gpu[:s])) / (1 - b2 ** s)
+        bound += lr * (A_m + np.abs(u_ref) * A_v) / (np.sqrt(v_gpu) + eps)
+        pr = pr_new
+        slack = bound + sum(tols[:s])  # plus the FP32 arithmetic of (a) at every step so far
+        d = np.abs(p_gpu[s] - pr)
+        assert np.all(d <= slack), (s, np.max(d / slack))
+    moved = np.abs(pr - p0)
+    print("Adam x%d: arithmetic max err/tol %.3f; gradient rel err max %.2e; trajectory |p_gpu - p_ref| "
+          "max %.2e (median bound %.2e, median move %.2e)" % (steps, worst_a, worst_g, np.max(d), np.median(bound),
+                                                          np.median(moved)))
+    net.close()
