@@ -218,6 +218,25 @@ int pm_observe_time_multi(pm_ctx *ctx, const pm_problem *p, const double *u, con
                           int n_obs, const int64_t *read_steps, int n_read, double kappa, double dt,
                           int64_t n_particles, uint64_t seed, double *mean, double *var);
 
+/* Replay of one path of Algorithm 1 (eq. euler): the positions X_0 .. X_{N_t}
+ * of particle i of observation j in the forward map
+ *   pm_observe_time(ctx, p, u, obs_pts, n_obs, kappa, T, dt, n_particles, seed, ...)
+ * on the same velocity engine, precision and step size T/N_t, N_t = ceil(T/dt).
+ * The path is re-run from x_j by the kernels of that map (with the Philox
+ * stream (seed, j, i)), carrying their own particle state (FP64; FP32 hi + lo
+ * pair; the matrix-core engine's 32-bit fixed-point fraction of the period),
+ * so path[N_t] equals that map's endpoints[j][i] bit for bit and every
+ * earlier row is the state the map held after that many steps.
+ *   j          0 <= j < n_obs, i: 0 <= i < n_particles
+ *   path       device [N_t + 1][2] FP64, each position wrapped to [0,1)^2
+ * Other arguments as for pm_observe_time (a PM_TORUS problem with theta0);
+ * N_t < PM_REPLAY_MAX_STEPS, else PM_EINVAL.  One wave of 64 particles runs
+ * N_t steps, so the call takes roughly the latency of N_t steps. */
+#define PM_REPLAY_MAX_STEPS (1 << 30)
+int pm_replay_path(pm_ctx *ctx, const pm_problem *p, const double *u, const double *obs_pts, int n_obs,
+                   double kappa, double T, double dt, int64_t n_particles, uint64_t seed, int j, int64_t i,
+                   double *path);
+
 /* Algorithm 2 (Section 3.2, Theorem 3.2) on the unit disk or the unit square:
  *   payoff_i = theta_dD(X_tau) - int_0^tau f(X_t) dt
  * with the exit detected after a step when Y is no longer inside (disk:

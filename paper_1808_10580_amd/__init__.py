@@ -88,6 +88,7 @@ def _declare(L):
     L.pm_observe_time_multi.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp, C.c_int, _d, _d, _i64, _u64,
                                         _vp, _vp]
     L.pm_jacobian_time.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _d, _i64, _u64, _d, _vp]
+    L.pm_replay_path.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _d, _i64, _u64, C.c_int, _i64, _vp]
     L.pm_observe_dirichlet_sources.argtypes = [_vp, _vp, _vp, C.POINTER(_Field), _vp, C.c_int, _d, _d, _i64,
                                                _u64, _i64, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.pm_observe_time_batch.argtypes = [_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.c_int, _d, _d, _d,
@@ -339,6 +340,21 @@ class Problem:
                                           _ptr(mean), _ptr(var))
         _check(st, "pm_observe_time_multi")
         return mean, var
+
+    def replay_path(self, u, obs, kappa, T, dt, n_particles, seed, j, i):
+        """Positions X_0..X_{N_t} of particle i of observation j in the map
+        observe_time(u, obs, kappa, T, dt, n_particles, seed): a CUDA float64
+        tensor [N_t + 1, 2], wrapped to [0,1)^2."""
+        torch = _torch()
+        self.ctx.bind_stream()
+        ut = self._u(u)
+        ob = _dev(obs, torch.float64, self.ctx.device).reshape(-1, 2)
+        nt = n_steps(float(T), float(dt))
+        path = torch.empty((nt + 1, 2), dtype=torch.float64, device=self.ctx.device)
+        st = _lib().pm_replay_path(self.ctx.h, self.h, _ptr(ut), _ptr(ob), ob.shape[0], float(kappa), float(T),
+                                   float(dt), int(n_particles), int(seed), int(j), int(i), _ptr(path))
+        _check(st, "pm_replay_path")
+        return path
 
     def jacobian_time(self, u, obs, kappa, T, dt, n_particles, seed, h):
         """Central-difference Jacobian dG/du [n_obs, 2M] with common random numbers (one batched launch)."""

@@ -342,7 +342,8 @@ void time_tuning(const pm_ctx *c, int K, int *ppl, int *src)
 // Algorithm 1 with the matrix-core velocity: one task per 64-particle chunk.
 int observe_time_hk(pm_ctx *c, const pm_problem *p, int n_u, const double *u, const int64_t *nps,
                     const uint64_t *seeds, const double *obs, int n_obs, double kappa, double dte,
-                    const int64_t *reads, int n_read, double *mean, double *var, double *endpoints)
+                    const int64_t *reads, int n_read, double *mean, double *var, double *endpoints,
+                    const Replay *rp = nullptr)
 {
     const int64_t Nt = reads[n_read - 1];
     const unsigned char *frag;
@@ -365,6 +366,16 @@ int observe_time_hk(pm_ctx *c, const pm_problem *p, int n_u, const double *u, co
     a.v0x = (float)p->v0[0];
     a.v0y = (float)p->v0[1];
     a.queue = c->d_queue;
+    if (rp) {  // one chunk, every step read out by one lane
+        a.rp = *rp;
+        a.n_read = (int)(Nt + 1);
+        a.np0 = nps[0];
+        a.seed0 = seeds[0];
+        a.n_tasks = 1;
+        if (launch_zero_u64(c->d_queue, 1, c->stream) != hipSuccess) return PM_EDEVICE;
+        if (launch_time_hk(a, c->n_cu, c->stream) != hipSuccess) return PM_EDEVICE;
+        return PM_OK;
+    }
 
     PayArgs pa{};
     pa.n_u = n_u;
@@ -463,13 +474,14 @@ int observe_time_hk(pm_ctx *c, const pm_problem *p, int n_u, const double *u, co
 template <typename T>
 int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, const int64_t *nps,
                       const uint64_t *seeds, const double *obs, int n_obs, double kappa, double dte,
-                      const int64_t *reads, int n_read, double *mean, double *var, double *endpoints)
+                      const int64_t *reads, int n_read, double *mean, double *var, double *endpoints,
+                      const Replay *rp = nullptr)
 {
     const int64_t Nt = reads[n_read - 1];
     if constexpr (std::is_same<T, float>::value) {
         if (p->hk)
             return observe_time_hk(c, p, n_u, u, nps, seeds, obs, n_obs, kappa, dte, reads, n_read, mean, var,
-                                   endpoints);
+                                   endpoints, rp);
     }
     bool mx = false;
     if constexpr (std::is_same<T, float>::value) mx = use_mx(c, p) && mx_step_ok(dte, kappa);
@@ -482,7 +494,7 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
 
     int ppl = 1, src = PM_COEF_LDS;  // the matrix-core kernel: one chunk per task
     if (!std::is_same<T, double>::value && !mx) {
-        if (n_read > 1) {
+        if (n_read > 1 || rp) {
             ppl = 2;  // the multi-readout kernel's one FP32 variant
             src = PM_COEF_SCALAR;
         } else {
@@ -502,6 +514,13 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
     a.v0x = (T)p->v0[0];
     a.v0y = (T)p->v0[1];
     a.queue = c->d_queue;
+    if (rp) {  // one chunk, every step read out by one lane
+        a.rp = *rp;
+        a.n_read = (int)(Nt + 1);
+        a.np0 = nps[0];
+        a.seed0 = seeds[0];
+        a.n_tasks = 1;
+    }
 
     PayArgs pa{};
     pa.n_u = n_u;
@@ -518,7 +537,9 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
 
     int64_t total_chunks;
     double steps = 0.0;
-    if (n_u == 1) {
+    if (rp) {
+        total_chunks = 0;
+    } else if (n_u == 1) {
         const int64_t cpo = (nps[0] + 63) / 64;
         total_chunks = cpo * n_obs;
         a.np0 = nps[0];
@@ -574,19 +595,21 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
         pa.chunk_off = a.chunk_off;
         pa.np_arr = a.np_arr;
     }
-    st = ensure(c, &c->part, &c->part_cap, (size_t)n_read * total_chunks * 3 * sizeof(double));
-    if (st) return st;
-    st = ensure(c, &c->states, &c->states_cap, (size_t)n_read * total_chunks * 64 * 2 * sizeof(double));
-    if (st) return st;
-    a.states = (double *)c->states;
-    a.read_stride = total_chunks * 64 * 2;
+    if (!rp) {
+        st = ensure(c, &c->part, &c->part_cap, (size_t)n_read * total_chunks * 3 * sizeof(double));
+        if (st) return st;
+        st = ensure(c, &c->states, &c->states_cap, (size_t)n_read * total_chunks * 64 * 2 * sizeof(double));
+        if (st) return st;
+        a.states = (double *)c->states;
+        a.read_stride = total_chunks * 64 * 2;
+    }
     pa.states = a.states;
     pa.n_chunks = total_chunks;
     pa.partials = (double *)c->part;
     fa.partials = pa.partials;
 
     if (launch_zero_u64(c->d_queue, 1, c->stream) != hipSuccess) return PM_EDEVICE;
-    if (!c->capturing) PM_HIP(hipEventRecord(c->ev0, c->stream));
+    if (!c->capturing && !rp) PM_HIP(hipEventRecord(c->ev0, c->stream));
     hipError_t le;
     if constexpr (std::is_same<T, float>::value) {
         if (mx) {
@@ -604,6 +627,7 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
         le = launch_time<T>(a, p->K, ppl, src, c->n_cu, c->bpc, c->stream);
     }
     if (le != hipSuccess) return PM_EDEVICE;
+    if (rp) return PM_OK;
     if (!c->capturing) {
         PM_HIP(hipEventRecord(c->ev1, c->stream));
         c->timed = true;
@@ -1097,6 +1121,37 @@ int pm_observe_time_multi(pm_ctx *c, const pm_problem *p, const double *u, const
                                          nullptr);
     return observe_time_core<float>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, dt, reads, n_read, mean, var,
                                     nullptr);
+}
+
+int pm_replay_path(pm_ctx *c, const pm_problem *p, const double *u, const double *obs, int n_obs,
+                   double kappa, double T, double dt, int64_t np, uint64_t seed, int j, int64_t i, double *path)
+{
+    if (!ctx_ok(c, p)) return PM_EINVAL;
+    if (p->domain != PM_TORUS || !p->has_theta0) return PM_EINVAL;
+    if ((p->n_modes > 0 && bad_ptr(u)) || bad_ptr(obs) || bad_ptr(path)) return PM_EINVAL;
+    if (n_obs < 1 || j < 0 || j >= n_obs) return PM_EINVAL;
+    if (np < 1 || np > ((int64_t)1 << 32) || i < 0 || i >= np) return PM_EINVAL;
+    if (check_time_args(kappa, T, dt)) return PM_EINVAL;
+    const int64_t Nt = n_steps_of(T, dt);
+    if (Nt >= PM_REPLAY_MAX_STEPS) return PM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
+    // the chunk of particle i as a one-chunk launch from x_j: Philox indices
+    // (i, j) through the offsets, the same kernels and step size as the map
+    Replay rp;
+    rp.i_off = (uint32_t)(i - i % 64);
+    rp.j_off = (uint32_t)j;
+    rp.lane = (int)(i % 64);
+    rp.out = path;
+    const int64_t np1 = 64;
+    const double dte = T / (double)Nt;
+    const int st = p->prec == PM_FP64
+                       ? observe_time_core<double>(c, p, 1, u, &np1, &seed, obs + 2 * (int64_t)j, 1, kappa, dte, &Nt,
+                                                   1, nullptr, nullptr, nullptr, &rp)
+                       : observe_time_core<float>(c, p, 1, u, &np1, &seed, obs + 2 * (int64_t)j, 1, kappa, dte, &Nt,
+                                                  1, nullptr, nullptr, nullptr, &rp);
+    if (st) return st;
+    if (launch_wrap_path(path, 2 * (Nt + 1), c->stream) != hipSuccess) return PM_EDEVICE;
+    return PM_OK;
 }
 
 int pm_jacobian_time(pm_ctx *c, const pm_problem *p, const double *u, const double *obs, int n_obs,

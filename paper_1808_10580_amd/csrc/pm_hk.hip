@@ -421,7 +421,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB == 2 ? 2
         const int64_t chv = wave_on ? ch : 0;
         const int64_t j = chv / cpo;
         const int64_t i = (chv - j * cpo) * 64 + part;
-        const uint32_t pi = (uint32_t)i, pj = (uint32_t)j;
+        const uint32_t pi = (uint32_t)i + a.rp.i_off, pj = (uint32_t)j + a.rp.j_off;
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
         const unsigned char *set = a.frag + (int64_t)b * a.set_bytes;
 
@@ -438,16 +438,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB == 2 ? 2
             y.wrap();
         };
         int r = 0;
-        int64_t next = a.read_at[0];
+        const bool rp = replay_on(a.rp);
+        int64_t next = rp ? 0 : a.read_at[0];
         auto readout = [&](int64_t done) {
             if (done == next) {
-                if (writer) {
+                if (rp) {
+                    if (writer && ch == 0 && part == a.rp.lane) {
+                        a.rp.out[2 * r] = x.value();
+                        a.rp.out[2 * r + 1] = y.value();
+                    }
+                } else if (writer) {
                     double *S = a.states + r * a.read_stride + 2 * ((cb + ch) * 64 + part);
                     S[0] = x.value();
                     S[1] = y.value();
                 }
                 ++r;
-                next = r < a.n_read ? a.read_at[r] : -1;
+                next = r < a.n_read ? (rp ? r : a.read_at[r]) : -1;
             }
         };
         readout(0);

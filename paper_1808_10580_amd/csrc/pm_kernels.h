@@ -25,6 +25,19 @@ struct FoldArgs {
     int64_t coef_stride;  // elements between parameter sets in the output
 };
 
+// Path replay through the multi-readout time kernels: the launch's
+// observation j and particle i run with Philox indices j + j_off and
+// i + i_off, and when `lane` >= 0 every step count 0..n_read-1 is a readout
+// whose position only the lane (particle offset within its chunk) `lane` of
+// chunk 0 writes, to out[2 r], out[2 r + 1] (read_at[] unused).
+struct Replay {
+    uint32_t i_off = 0, j_off = 0;
+    int lane = -1;
+    double *out = nullptr;
+};
+
+__host__ __device__ __forceinline__ bool replay_on(const Replay &r) { return r.lane >= 0; }
+
 template <typename T>
 struct TimeArgs {
     const T *coef;
@@ -47,6 +60,7 @@ struct TimeArgs {
     unsigned long long *queue;
     int n_read;                      // >= 1; read_at[n_read - 1] == n_steps
     int64_t read_at[PM_MAX_READS];   // increasing step counts of the readouts
+    Replay rp;                       // path replay (multi-readout kernels only)
 };
 
 struct PayArgs {
@@ -191,6 +205,7 @@ struct HkTimeArgs {
     unsigned long long *queue;
     int n_read;
     int64_t read_at[PM_MAX_READS];
+    Replay rp;
 };
 
 struct HkStepArgs {
@@ -236,6 +251,9 @@ hipError_t launch_dirichlet(const DirArgs<T> &a, int K, int fk, int src, int n_c
                             hipStream_t st);
 hipError_t launch_dir_payoff(const DirPayArgs &a, hipStream_t st);
 hipError_t launch_time_payoff(const PayArgs &a, hipStream_t st);
+// A replayed path onto the torus' unit square, in place: X <- X - floor(X)
+// (the same map as the endpoints of launch_time_payoff).
+hipError_t launch_wrap_path(double *path, int64_t n_values, hipStream_t st);
 hipError_t launch_chunk_reduce(const double *vals, int64_t np, int n_obs, double *partials,
                                unsigned *flags, hipStream_t st);
 hipError_t launch_finalize(const FinalArgs &a, int n_groups, hipStream_t st);

@@ -176,8 +176,8 @@ __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
             const int64_t q = cc - j * cpo;
             const int64_t i = q * 64 + lane;
             act[p] = cval[p] && i < np;
-            pi[p] = (uint32_t)i;
-            pj[p] = (uint32_t)j;
+            pi[p] = (uint32_t)i + a.rp.i_off;
+            pj[p] = (uint32_t)j + a.rp.j_off;
             x[p].set(a.obs[2 * j]);
             y[p].set(a.obs[2 * j + 1]);
         }
@@ -245,19 +245,27 @@ __global__ __launch_bounds__(256) void k_time(const TimeArgs<T> a)
             // steps the positions go to slot r ([r][global chunk][lane]).  The
             // step count is wave-uniform, so the check is a scalar compare.
             int r = 0;
-            int64_t next = a.read_at[0];
+            const bool rp = replay_on(a.rp);
+            int64_t next = rp ? 0 : a.read_at[0];
             auto readout = [&](int64_t done) {
                 if (done == next) {
+                    if (rp) {
+                        if (cval[0] && cix[0] == 0 && lane == a.rp.lane) {
+                            a.rp.out[2 * r] = x[0].value();
+                            a.rp.out[2 * r + 1] = y[0].value();
+                        }
+                    } else {
 #pragma unroll
-                    for (int p = 0; p < PPL; ++p) {
-                        if (cval[p]) {
-                            double *S = a.states + r * a.read_stride + 2 * ((cb + cix[p]) * 64 + lane);
-                            S[0] = x[p].value();
-                            S[1] = y[p].value();
+                        for (int p = 0; p < PPL; ++p) {
+                            if (cval[p]) {
+                                double *S = a.states + r * a.read_stride + 2 * ((cb + cix[p]) * 64 + lane);
+                                S[0] = x[p].value();
+                                S[1] = y[p].value();
+                            }
                         }
                     }
                     ++r;
-                    next = r < a.n_read ? a.read_at[r] : -1;
+                    next = r < a.n_read ? (rp ? r : a.read_at[r]) : -1;
                 }
             };
 
@@ -834,6 +842,19 @@ hipError_t launch_time_payoff(const PayArgs &a, hipStream_t st)
 {
     const int64_t blocks = (a.n_read * a.n_chunks + 3) / 4;
     hipLaunchKernelGGL(k_time_payoff, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_wrap_path(double *__restrict__ v, int64_t n)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) v[e] -= floor(v[e]);
+}
+
+hipError_t launch_wrap_path(double *path, int64_t n_values, hipStream_t st)
+{
+    if (n_values < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_wrap_path, dim3((unsigned)((n_values + 255) / 256)), dim3(256), 0, st, path, n_values);
     return hipGetLastError();
 }
 

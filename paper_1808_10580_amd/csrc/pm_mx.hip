@@ -509,7 +509,7 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
         const int64_t ch = task - tb;  // chunk within the set (< cpo * n_obs)
         const int64_t j = ch / cpo;
         const int64_t i = (ch - j * cpo) * 64 + lane;
-        const uint32_t pi = (uint32_t)i, pj = (uint32_t)j;
+        const uint32_t pi = (uint32_t)i + a.rp.i_off, pj = (uint32_t)j + a.rp.j_off;
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 
         FixCoord x, y;
@@ -517,14 +517,22 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
         y.set(a.obs[2 * j + 1]);
 
         int r = 0;
-        int64_t next = a.read_at[0];
+        const bool rp = MT && replay_on(a.rp);
+        int64_t next = rp ? 0 : a.read_at[0];
         auto readout = [&](int64_t done) {
             if (MT && done == next) {
-                double *S = a.states + r * a.read_stride + 2 * ((cb + ch) * 64 + lane);
-                S[0] = x.value();
-                S[1] = y.value();
+                if (rp) {
+                    if (ch == 0 && lane == a.rp.lane) {
+                        a.rp.out[2 * r] = x.value();
+                        a.rp.out[2 * r + 1] = y.value();
+                    }
+                } else {
+                    double *S = a.states + r * a.read_stride + 2 * ((cb + ch) * 64 + lane);
+                    S[0] = x.value();
+                    S[1] = y.value();
+                }
                 ++r;
-                next = r < a.n_read ? a.read_at[r] : -1;
+                next = r < a.n_read ? (rp ? r : a.read_at[r]) : -1;
             }
         };
         readout(0);
