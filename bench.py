@@ -11,10 +11,14 @@ each step ends when the 49 means are back on the host (as an MCMC step needs).
 
 Prints one JSON line:
   value            particle-steps/s over the K timed steps (wall clock)
-  roofline         the time kernel's algorithmic FP32 FLOP rate from HIP
-                   events on its stream against the chip's FP32 vector peak
-                   (with the matrix-core engine also its issued FP16 matrix
-                   FLOP rate against the dense FP16 peak)
+  roofline         the time kernel's rate in algorithmic FLOPs -- the
+                   mode-by-mode sum of eq. v_expand, 14 FLOP per mode, 12 per
+                   harmonic, 20 for the update and the normals -- from HIP
+                   events on its stream, against the peak of the unit that
+                   runs the velocity contraction (the dense FP16 matrix peak
+                   for the default matrix-core engine, the FP32 vector peak
+                   for the vector engine); beside it the FLOPs the kernel
+                   executes and, from rocprofv3 counters, what limits it
   cpu_baseline     the FP64 CPU oracle on a bounded sample of the same workload
 """
 from __future__ import annotations
@@ -69,6 +73,18 @@ KERNEL_SOURCES = {
 MX_ISSUED_FLOP_PER_PARTICLE_STEP = 2 * 3 * 2 * 32 * 32 * 16 // 64
 PEAK_FP16_DENSE_TFLOPS = 2500.0
 
+# rocprofv3 counters of the time kernel on the main workload (per particle-step:
+# counter x 64 lanes / 4.9e9), valid for the sources they were taken on.
+# Keys: VALU instructions, VALU issue slots (multi-cycle operations count their
+# extra cycles), FP32 FMA / MUL / ADD instructions, matrix-core busy fraction,
+# and the fraction of the kernel's cycles one VALU issue port needs for the
+# slots (slots x 4 cycles per wave64 slot / 64 lanes per wave, over the
+# kernel's cycles per SIMD).
+COUNTERS = {
+    "mfma": (None, ""),
+    "valu": (None, ""),
+}
+
 
 def kernel_sources_sha256(engine: str = "valu") -> str:
     import hashlib
@@ -112,33 +128,75 @@ def engine_in_use(pm, engine_arg: str, K: int, domain: str = "torus") -> str:
     return "mfma"
 
 
-def kernel_roofline(engine: str, K: int, fl: int, steps: float, kern_s: float, traffic):
+def counters(engine: str):
+    """The recorded counter figures of the time kernel, or None once its
+    sources have changed since they were taken."""
+    fig, sha = COUNTERS[engine]
+    if fig is None or kernel_sources_sha256(engine) != sha:
+        return None
+    return fig
+
+
+def kernel_roofline(engine: str, K: int, fl: int, fl_exec: int, steps: float, kern_s: float, traffic):
+    """Roofline of the time kernel.  `fl`: algorithmic FLOPs per particle-step
+    (the mode-by-mode sum); `fl_exec`: the FP32-equivalent FLOPs the kernel's
+    tensor-product velocity executes.  The bound is the unit that runs the
+    velocity contraction: the FP16 matrix cores (split FP16 x3, FP32
+    accumulation) for the matrix-core engine, the FP32 vector units otherwise."""
     achieved = fl * steps / kern_s / 1e12
-    rl = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-          "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "traffic_unit": "bytes per launch",
-          "kernel": "k_time_mx<%d>" % K if engine == "mfma" else "k_time<float,%d>" % K,
-          "kernel_ms": round(kern_s * 1e3, 3), "flop_per_particle_step": fl, "engine": engine}
-    if engine == "mfma":
+    mx = engine == "mfma"
+    peak = PEAK_FP16_DENSE_TFLOPS if mx else PEAK_FP32_TFLOPS
+    rl = {"bound": "mfma" if mx else "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+          "frac": round(achieved / peak, 4), "traffic": traffic, "traffic_unit": "bytes per launch",
+          "peak_of": "dense FP16 matrix" if mx else "FP32 vector (256 CU x 2.4 GHz x 256 FLOP/clk)",
+          "kernel": "k_time_mx<%d>" % K if mx else "k_time<float,%d>" % K,
+          "kernel_ms": round(kern_s * 1e3, 3), "flop_per_particle_step": fl,
+          "flop_count": "mode sum of eq. v_expand: 14 per mode + 12 per harmonic + 20 (update, normals)",
+          "executed_flop_per_particle_step": fl_exec,
+          "executed_tflops": round(fl_exec * steps / kern_s / 1e12, 3), "engine": engine}
+    if mx:
         issued = MX_ISSUED_FLOP_PER_PARTICLE_STEP * steps / kern_s / 1e12
         rl["matrix_cores"] = {"contraction": "split FP16 x3 (hi*hi + hi*lo + lo*hi), FP32 accumulate",
-                              "issued_tflops": round(issued, 2), "peak_fp16_dense": PEAK_FP16_DENSE_TFLOPS,
-                              "frac": round(issued / PEAK_FP16_DENSE_TFLOPS, 4)}
+                              "issued_tflops": round(issued, 2), "frac_issued": round(issued / PEAK_FP16_DENSE_TFLOPS, 4)}
+    c = counters(engine)
+    if c is not None:
+        fp32 = (2 * c["fma_f32"] + c["mul_f32"] + c["add_f32"]) * steps / kern_s / 1e12
+        rl["limiter"] = {"unit": "VALU issue", "valu_insts_per_particle_step": c["valu_insts"],
+                         "valu_issue_slots_per_particle_step": c["valu_slots"],
+                         "one_port_issue_frac": c["issue_frac"], "matrix_core_busy": c.get("mfma_busy"),
+                         "counted_fp32_valu_tflops": round(fp32, 2),
+                         "counted_fp32_valu_frac": round(fp32 / PEAK_FP32_TFLOPS, 4),
+                         "source": c["source"]}
     return rl
 
 
+def alg_flops_per_particle_step(n_modes: int, K: int, domain: str = "torus") -> int:
+    """Algorithmic FLOPs of one Euler-Maruyama step (FMA = 2) by the method's
+    own arithmetic, the mode-by-mode sum of eq. v_expand: per mode the
+    sine and cosine of 2 pi k.x from the axis values by angle addition
+    (6 FLOP) and two FMAs per velocity component (8); per harmonic of each
+    axis one angle-addition step (6 FLOP per axis, 12 per harmonic); the
+    update and Box-Muller arithmetic 20.  The disk's stream function carries a
+    third form (psi itself, for the cutoff's product rule: 4 more per mode)
+    and the cutoff (16 more).  The hardware transcendentals and the Philox
+    integer work carry no FLOPs."""
+    if domain == "disk":
+        return 18 * n_modes + 12 * K + 36
+    return 14 * n_modes + 12 * K + 20
+
+
 def flops_per_particle_step(K: int) -> int:
-    """Algorithmic FP32 FLOPs of one Euler-Maruyama step of the time kernel
-    (FMA = 2).  Trig basis: per axis K-1 angle-addition harmonics of 2 mul +
-    2 FMA (the per-harmonic cost the count is defined with; the kernels now
-    take the harmonics from the three-term recurrence, 4 (K-1) FLOP per axis,
-    so they execute 20 FLOP fewer than counted at K = 6).  Velocity: two bilinear forms phi(x)^T C phi(y) over B = 2K+1
-    basis functions per axis; row j = 0 carries only the y form (1 mul +
-    (B-2) FMA), rows j >= 1 carry both (x: B-1 FMA, y: 1 mul + B-2 FMA) and
-    two FMAs into (v_x, v_y).  Update: 1 add + 2 FMA per axis.  Box-Muller
-    arithmetic: 1 FMA + 4 mul per normal pair.  The 8 hardware
-    transcendentals and the Philox integer work are not counted."""
+    """FP32-equivalent FLOPs the tensor-product time kernels execute per
+    Euler-Maruyama step (FMA = 2).  Trig basis: per axis K-1 three-term
+    recurrence harmonics of 2 FMA (4 FLOP) after one sin/cos pair.  Velocity:
+    two bilinear forms phi(x)^T C phi(y) over B = 2K+1 basis functions per
+    axis; row j = 0 carries only the y form (1 mul + (B-2) FMA), rows j >= 1
+    carry both (x: B-1 FMA, y: 1 mul + B-2 FMA) and two FMAs into (v_x, v_y).
+    Update: 1 add + 2 FMA per axis.  Box-Muller arithmetic: 1 FMA + 4 mul per
+    normal pair.  The 8 hardware transcendentals and the Philox integer work
+    are not counted."""
     B = 2 * K + 1
-    basis = 2 * (K - 1) * (2 * 1 + 2 * 2)
+    basis = 2 * (K - 1) * 4
     row0 = 1 + 2 * (B - 2)
     row = 2 * (B - 1) + (1 + 2 * (B - 2)) + 2 * 2
     contraction = row0 + (B - 1) * row
@@ -148,14 +206,14 @@ def flops_per_particle_step(K: int) -> int:
 
 
 def flops_per_particle_step_disk(K: int) -> int:
-    """Algorithmic FP32 FLOPs of one step of the Dirichlet walk on the disk:
+    """FP32-equivalent FLOPs one step of the Dirichlet walk on the disk executes:
     three bilinear forms (psi_F and its two derivatives) over B = 2K+1 basis
     functions, 3 (B-1) + 3 FMA per row; the trig basis as on the torus; the
     cutoff (1 - r^2)^2 and its product rule (13); the update and Box-Muller
     arithmetic as on the torus.  The FP64 exit test and source sum are not
     counted."""
     B = 2 * K + 1
-    basis = 2 * (K - 1) * (2 * 1 + 2 * 2)
+    basis = 2 * (K - 1) * 4
     contraction = B * (3 * (B - 1) + 3) * 2
     return basis + contraction + 13 + 2 * (1 + 2 * 2) + (2 + 4)
 
@@ -167,6 +225,19 @@ def flops_per_particle_step_mfma(K: int) -> int:
     32 x 16 is not counted."""
     B = 2 * K + 1
     return 3 * 2 * B * B * 2
+
+
+def dtype_label(engine: str) -> str:
+    """What the velocity contraction computes in: FP16 hi + lo operand pairs,
+    three products with FP32 accumulation on the matrix cores, or FP32 FMAs."""
+    return "f16x3-split/f32-acc" if engine == "mfma" else "f32"
+
+
+DTYPE_DETAIL = {
+    "mfma": "velocity contraction on the matrix cores in split FP16 (hi*hi + hi*lo + lo*hi, FP32 accumulate); "
+            "bases, y form and normals FP32; particle state 32-bit fixed point; payoffs and statistics FP64",
+    "valu": "velocity, bases and normals FP32; particle state FP32 hi + lo pair; payoffs and statistics FP64",
+}
 
 
 def cpu_baseline(wl, n_particles: int):
@@ -272,9 +343,16 @@ def bench_other(args):
             if ctx.sync() != pm.PM_OK:
                 raise pm.PMError(ctx.sync(), "forward map")
         K = int(abs(wl.modes).max())
-        fl = flops_per_particle_step_mfma(K)
-        rl = {"bound": "mfma", "peak": 2500.0, "unit": "TFLOP/s", "kernel": f"k_time_hk<{(2 * K + 32) // 32}>",
-              "flop_per_particle_step": fl, "dtype_of_peak": "fp16 dense"}
+        fl = alg_flops_per_particle_step(len(wl.modes), K)
+        B = 2 * K + 1
+        rl = {"bound": "mfma", "peak": PEAK_FP16_DENSE_TFLOPS, "unit": "TFLOP/s",
+              "kernel": f"k_time_hk<{(2 * K + 32) // 32}>", "flop_per_particle_step": fl,
+              "flop_count": "mode sum of eq. v_expand: 14 per mode + 12 per harmonic + 20 (update, normals)",
+              "peak_of": "dense FP16 matrix",
+              # the tensor-product contraction, one product per term (2 forms x B^2 multiply-adds)
+              "executed_flop_per_particle_step": 2 * B * B * 2,
+              # the same with the three split-FP16 products per term
+              "issued_flop_per_particle_step": flops_per_particle_step_mfma(K)}
         traffic = other_traffic(name, "mfma")
         desc = ("torus-k80-turbulent: |k|_2<=80 (10,040 modes, 20,080 coefficients), kappa=3e-5, 2 points x 1e5 "
                 "particles, 4,800 steps (dt=1/9600) read out at 13 times in [0, 0.5], FP32 states, split-FP16 "
@@ -304,11 +382,15 @@ def bench_other(args):
                 raise pm.PMError(st, "forward map")
             last["steps"] = float((tau / wl.dt).sum() * wl.n_particles)
         K = int(abs(wl.modes).max())
-        fl = flops_per_particle_step_disk(K)
+        fl = alg_flops_per_particle_step(len(wl.modes), K, "disk")
         eng = engine_in_use(pm, args.engine, K, "disk")
-        rl = {"bound": "alu", "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-              "kernel": f"k_dirichlet_mx<{K}>" if eng == "mfma" else f"k_dirichlet<float,{K}>",
-              "flop_per_particle_step": fl, "velocity_engine": eng}
+        mx = eng == "mfma"
+        rl = {"bound": "mfma" if mx else "alu", "peak": PEAK_FP16_DENSE_TFLOPS if mx else PEAK_FP32_TFLOPS,
+              "unit": "TFLOP/s", "kernel": f"k_dirichlet_mx<{K}>" if mx else f"k_dirichlet<float,{K}>",
+              "flop_per_particle_step": fl,
+              "flop_count": "mode sum of eq. v_expand with the disk cutoff: 18 per mode + 12 per harmonic + 36",
+              "peak_of": "dense FP16 matrix" if mx else "FP32 vector",
+              "executed_flop_per_particle_step": flops_per_particle_step_disk(K), "velocity_engine": eng}
         traffic = other_traffic(name, eng)
         desc = ("disk-dirichlet: unit disk, 64-coefficient stream function x (1-r^2)^2, kappa=0.02, g=cos 3phi, "
                 "f=-1, 25 points x 5e4 particles, dt=1e-4, walks until exit, FP32 states + FP64 exit test")
@@ -327,7 +409,7 @@ def bench_other(args):
             m.cpu()
             if ctx.sync() != pm.PM_OK:
                 raise pm.PMError(ctx.sync(), "forward map")
-        fl = flops_per_particle_step(K)
+        fl = alg_flops_per_particle_step(len(wl.modes), K)
         rl = {"engine": engine}
         desc = ("torus-k6-batch: 512 pCN proposals (beta 0.2) of the |k|_inf<=6 problem in one launch, per-set "
                 "particle counts log-uniform in [1e3, 1e5], 49 points, 1000 steps")
@@ -336,24 +418,60 @@ def bench_other(args):
         sys.exit(2)
 
     elapsed, kernel_ms, work = _time_steps(run, args.steps, args.warmup, ctx)
+    tail = None
     if name == "disk-dirichlet":
         steps_per_map = last["steps"]
+        tail = disk_tail_bound(pm, ctx, prob, wl, u, obs, sum(kernel_ms) / len(kernel_ms) / 1e3)
     else:
         steps_per_map = work[-1]
     kern_s = sum(kernel_ms) / len(kernel_ms) / 1e3
     if "engine" in rl:
-        rl = kernel_roofline(rl["engine"], K, fl, steps_per_map, kern_s, None)
+        engine = rl["engine"]
+        rl = kernel_roofline(engine, K, fl, flops_per_particle_step(K), steps_per_map, kern_s, None)
+        dt_label = dtype_label(engine)
     else:
         achieved = fl * steps_per_map / kern_s / 1e12
         rl.update({"achieved": round(achieved, 3), "frac": round(achieved / rl["peak"], 4), "traffic": traffic,
-                   "traffic_unit": "bytes per launch", "kernel_ms": round(kern_s * 1e3, 3)})
+                   "traffic_unit": "bytes per launch", "kernel_ms": round(kern_s * 1e3, 3),
+                   "executed_tflops": round(rl["executed_flop_per_particle_step"] * steps_per_map / kern_s / 1e12,
+                                            3)})
+        if rl["bound"] == "mfma":
+            rl["frac_of_fp32_vector_peak"] = round(achieved / PEAK_FP32_TFLOPS, 4)
+        dt_label = dtype_label(rl.get("velocity_engine", "mfma"))
     out = {"metric": "particle-steps/s at 1 GPU", "value": steps_per_map * args.steps / elapsed,
            "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "vs_baseline": None, "dtype": dt_label, "data": "synthetic",
            "config": {"workload": desc, "particle_steps_per_step": steps_per_map},
            "roofline": rl, "cpu_baseline": cpu}
+    if tail is not None:
+        out["tail"] = tail
     print(json.dumps(out))
+
+
+def disk_tail_bound(pm, ctx, prob, wl, u, obs, map_s):
+    """How far the longest walk bounds the disk map: the exit steps of one
+    map (its paths), then one walker alone for as many steps as the longest
+    walk took (a start at the centre with a step so small that it cannot
+    leave, capped at that count), timed by the kernel's HIP events."""
+    import numpy as np
+    import torch
+    out = prob.observe_dirichlet(u, wl.f, wl.g, obs, wl.kappa, wl.dt, wl.n_particles, wl.seed, wl.max_steps,
+                                 paths=True)
+    steps = out["paths"][..., 3].cpu().numpy().reshape(-1)
+    ctx.sync()
+    n_max = int(steps.max())
+    centre = torch.zeros((1, 2), dtype=torch.float64, device=obs.device)
+    prob.observe_dirichlet(u, wl.f, wl.g, centre, wl.kappa, 1e-12, 1, wl.seed, n_max)
+    st = ctx.sync()
+    if st not in (pm.PM_OK, pm.PM_ECAPPED):
+        raise pm.PMError(st, "lone walk")
+    lone_ms, lone_steps = ctx.last_kernel_stats()
+    q = np.quantile(steps, [0.5, 0.95, 0.99])
+    return {"exit_steps_median": float(q[0]), "exit_steps_p95": float(q[1]), "exit_steps_p99": float(q[2]),
+            "exit_steps_max": n_max, "lone_walk_ms": round(lone_ms, 3), "map_ms": round(map_s * 1e3, 3),
+            "lone_walk_frac_of_map": round(lone_ms / (map_s * 1e3), 4),
+            "lone_walk_ns_per_step": round(lone_ms * 1e6 / max(n_max, 1), 2)}
 
 
 def main():
@@ -436,9 +554,10 @@ def main():
     print(f"[bench] {args.steps} maps in {elapsed:.3f} s; time kernel {min(kernel_ms):.2f}-"
           f"{max(kernel_ms):.2f} ms", file=sys.stderr)
 
-    fl = flops_per_particle_step(K)
+    fl = alg_flops_per_particle_step(len(wl.modes), K)
     kern_s = sum(kernel_ms) / len(kernel_ms) / 1e3
-    roofline = kernel_roofline(engine, K, fl, steps_per_map, kern_s, counter_traffic(engine))
+    roofline = kernel_roofline(engine, K, fl, flops_per_particle_step(K), steps_per_map, kern_s,
+                               counter_traffic(engine))
     if engine == "valu":
         roofline["variant"] = tuned if tuned else {"particles_per_lane": args.ppl or 2,
                                                    "coef_source": args.coef_source}
@@ -458,7 +577,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype_label(engine),
+        "dtype_detail": DTYPE_DETAIL[engine],
         "data": "synthetic",
         "config": {"workload": "torus-k6-fp32: 2D torus, |k|_inf<=6 stream function (168 coefficients), "
                                "kappa=0.01, theta0 = 3 periodised Gaussian bumps, 7x7 grid x 1e5 particles, "
