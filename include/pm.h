@@ -341,7 +341,7 @@ int pm_set_tuning(pm_ctx *ctx, int particles_per_lane, int coef_source);
  *     velocity errors near 1e-6 of max |v|, paths within the FP32 error
  *     contract);
  *   PM_ENGINE_VALU: FP32 fused multiply-adds on the vector units (the
- *     kernel that pm_set_tuning and pm_autotune_time tune).
+ *     kernel whose variants pm_set_tuning selects).
  * The matrix-core kernels keep particle coordinates as 32-bit fixed-point
  * numbers: on the torus fractions of the period (resolution 2^-32, the wrap
  * by modular overflow), on the disk multiples of 2^-30 with each step's
@@ -379,16 +379,24 @@ int pm_set_dirichlet_blocks_per_cu(pm_ctx *ctx, int blocks_per_cu);
  * whose tails are wide rather than long. */
 int pm_set_dirichlet_compaction(pm_ctx *ctx, int dump_below, int launches);
 
-/* Autotuner for the time kernel (Algorithm 1): times every particles-per-lane
- * and coefficient-source variant on a probe of n_probe_steps steps with the
- * given particle count and stores the fastest for this problem's K in the
- * context (used whenever pm_set_tuning's particles_per_lane is 0).  Results
- * are bitwise identical for every variant, so tuning never changes G(u).
- * Synchronous.  Outputs (host, nullable): chosen particles per lane,
- * coefficient source and the probe time in milliseconds. */
+/* Autotuner for the time kernel (Algorithm 1) of an FP32 problem: times each
+ * variant of the kernel the context would run for it on a probe of
+ * n_probe_steps steps with the given particle count and stores the fastest
+ * for this problem's K in the context.
+ *   vector engine: every particles-per-lane (1-4) and coefficient-source
+ *     variant (used whenever pm_set_tuning's particles_per_lane is 0);
+ *   matrix-core engine (K <= PM_MAX_K_MX): the persistent grid's blocks per
+ *     compute unit, 1-8 (used whenever pm_set_blocks_per_cu is 0; a value at
+ *     or above the occupancy limit runs as that limit).
+ * Results are bitwise identical for every variant, so tuning never changes
+ * G(u).  FP64 and high-K problems have one variant (nothing is timed).
+ * Synchronous.  Outputs (host, nullable): particles per lane, coefficient
+ * source, blocks per compute unit (0 = occupancy limit) and the probe time in
+ * milliseconds. */
 int pm_autotune_time(pm_ctx *ctx, const pm_problem *p, const double *u, const double *obs_pts,
                      int n_obs, double kappa, double dt, int64_t n_particles, uint64_t seed,
-                     int n_probe_steps, int *particles_per_lane, int *coef_source, double *probe_ms);
+                     int n_probe_steps, int *particles_per_lane, int *coef_source, int *blocks_per_cu,
+                     double *probe_ms);
 
 /* Captured forward map.  Records the whole of one pm_observe_time_batch call
  * (coefficient fold, persistent time kernel, payoff/chunk reduction and

@@ -105,7 +105,7 @@ def _declare(L):
     L.pm_set_dirichlet_blocks_per_cu.argtypes = [_vp, C.c_int]
     L.pm_set_dirichlet_compaction.argtypes = [_vp, C.c_int, C.c_int]
     L.pm_autotune_time.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _i64, _u64, C.c_int,
-                                   C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(_d)]
+                                   C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(_d)]
     L.pm_graph_create_time.argtypes = [_vp, _vp, C.c_int, _vp, _vp, _vp, _vp, C.c_int, _d, _d, _d,
                                        _vp, _vp, C.POINTER(_vp)]
     L.pm_graph_launch.argtypes = [_vp]
@@ -386,17 +386,20 @@ class Problem:
         return mean, var
 
     def autotune_time(self, u, obs, kappa, dt, n_particles, seed=1, n_probe_steps=100):
-        """Time every kernel variant on a probe and keep the fastest for this K."""
+        """Time every variant of the kernel this problem runs on (vector engine:
+        particles per lane and coefficient source; matrix-core engine: blocks
+        per compute unit) on a probe and keep the fastest for this K."""
         torch = _torch()
         self.ctx.bind_stream()
         ut = self._u(u)
         ob = _dev(obs, torch.float64, self.ctx.device).reshape(-1, 2)
-        ppl, src, ms = C.c_int(), C.c_int(), C.c_double()
+        ppl, src, bpc, ms = C.c_int(), C.c_int(), C.c_int(), C.c_double()
         st = _lib().pm_autotune_time(self.ctx.h, self.h, _ptr(ut), _ptr(ob), ob.shape[0], float(kappa),
                                      float(dt), int(n_particles), int(seed), int(n_probe_steps),
-                                     C.byref(ppl), C.byref(src), C.byref(ms))
+                                     C.byref(ppl), C.byref(src), C.byref(bpc), C.byref(ms))
         _check(st, "pm_autotune_time")
-        return {"particles_per_lane": ppl.value, "coef_source": src.value, "probe_ms": ms.value}
+        return {"particles_per_lane": ppl.value, "coef_source": src.value, "blocks_per_cu": bpc.value,
+                "probe_ms": ms.value}
 
     def graph_time(self, u, obs, kappa, T, dt, n_particles, seeds) -> "Graph":
         """Capture pm_observe_time_batch (n_u = len(n_particles)) as a replayable graph.

@@ -123,6 +123,7 @@ struct pm_ctx {
     size_t mx_cap = 0;
     int tune_ppl[PM_MAX_K + 1] = {0};  // autotuned choice per harmonic count K
     int tune_src[PM_MAX_K + 1] = {0};
+    int tune_bpc_mx[PM_MAX_K_MX + 1] = {0};  // autotuned persistent grid of the small-K matrix-core kernel
     bool capturing = false;  // recording a graph: no timing events, no host waits
     // pm_observe_time_noalloc: the per-call buffers point into the fixed
     // scratch for the duration of the call, and ensure() may not allocate
@@ -619,7 +620,7 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
             ma.sets = mx_sets;
             ma.vmax_fast = (float)((0.45 - 5.9 * std::sqrt(2.0 * kappa * dte)) / dte -
                                    std::max(std::fabs(p->v0[0]), std::fabs(p->v0[1])));
-            le = launch_time_mx(ma, p->K, c->n_cu, c->bpc, c->stream);
+            le = launch_time_mx(ma, p->K, c->n_cu, c->bpc ? c->bpc : c->tune_bpc_mx[p->K], c->stream);
         } else {
             le = launch_time<T>(a, p->K, ppl, src, c->n_cu, c->bpc, c->stream);
         }
@@ -1543,9 +1544,28 @@ void pm_graph_destroy(pm_graph *g)
     delete g;
 }
 
+// Fastest probe time (ms, best of two) of the forward map with the context's
+// current settings.
+static int probe_ms(pm_ctx *c, const pm_problem *p, const double *u, const double *obs, int n_obs, double kappa,
+                    double T, double dt, int64_t np, uint64_t seed, double *tmp, double *out)
+{
+    double ms_best = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+        int st = observe_time_impl<float>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, T, dt, tmp, tmp + n_obs,
+                                          nullptr);
+        if (st) return st;
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return PM_EDEVICE;
+        float f = 0.f;
+        if (hipEventElapsedTime(&f, c->ev0, c->ev1) != hipSuccess) return PM_EDEVICE;
+        if (f < ms_best) ms_best = f;
+    }
+    *out = ms_best;
+    return PM_OK;
+}
+
 int pm_autotune_time(pm_ctx *c, const pm_problem *p, const double *u, const double *obs, int n_obs,
                      double kappa, double dt, int64_t np, uint64_t seed, int n_probe_steps,
-                     int *ppl_out, int *src_out, double *ms_out)
+                     int *ppl_out, int *src_out, int *bpc_out, double *ms_out)
 {
     if (!ctx_ok(c, p)) return PM_EINVAL;
     if (p->domain != PM_TORUS || !p->has_theta0) return PM_EINVAL;
@@ -1553,43 +1573,50 @@ int pm_autotune_time(pm_ctx *c, const pm_problem *p, const double *u, const doub
     if (np < 1 || np > ((int64_t)1 << 32) || n_probe_steps < 1) return PM_EINVAL;
     if (!(std::isfinite(kappa) && kappa >= 0.0) || !finite_pos(dt)) return PM_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return PM_EDEVICE;
-    if (p->prec == PM_FP64 || p->hk) {  // one compiled variant
-        if (ppl_out) *ppl_out = 1;
-        if (src_out) *src_out = PM_COEF_LDS;
-        if (ms_out) *ms_out = 0.0;
-        return PM_OK;
-    }
+    if (ppl_out) *ppl_out = 1;
+    if (src_out) *src_out = PM_COEF_LDS;
+    if (bpc_out) *bpc_out = 0;
+    if (ms_out) *ms_out = 0.0;
+    if (p->prec == PM_FP64 || p->hk) return PM_OK;  // one compiled variant
+    const bool mx = use_mx(c, p) && mx_step_ok(dt, kappa);
     double *tmp = nullptr;
     if (hipMalloc((void **)&tmp, 2 * (size_t)n_obs * sizeof(double)) != hipSuccess) return PM_ENOMEM;
-    const int save_ppl = c->ppl, save_src = c->src, save_engine = c->engine;
-    c->engine = PM_ENGINE_VALU;  // the probes time the vector kernel's variants
+    const int save_ppl = c->ppl, save_src = c->src, save_bpc = c->bpc;
     const double T = n_probe_steps * dt;
-    int best_ppl = 2, best_src = PM_COEF_LDS;
     double best = 1e300;
     int st = PM_OK;
+    if (mx) {
+        // the matrix-core kernel: persistent blocks per compute unit (a
+        // value at or above the occupancy limit runs as that limit)
+        int best_bpc = 0;
+        for (int bpc = 1; bpc <= 8 && st == PM_OK; ++bpc) {
+            c->bpc = bpc;
+            double ms = 0.0;
+            st = probe_ms(c, p, u, obs, n_obs, kappa, T, dt, np, seed, tmp, &ms);
+            if (st == PM_OK && ms < best) {
+                best = ms;
+                best_bpc = bpc;
+            }
+        }
+        c->bpc = save_bpc;
+        (void)hipFree(tmp);
+        if (st) return st;
+        c->tune_bpc_mx[p->K] = best_bpc;
+        if (bpc_out) *bpc_out = best_bpc;
+        if (ms_out) *ms_out = best;
+        return PM_OK;
+    }
+    // the vector kernel: particles per lane and coefficient source
+    int best_ppl = 2, best_src = PM_COEF_LDS;
     const int ppls[4] = {1, 2, 3, 4};
     for (int src = 0; src < 2 && st == PM_OK; ++src) {
         for (int pi = 0; pi < 4 && st == PM_OK; ++pi) {
             c->ppl = ppls[pi];
             c->src = src;
-            double ms_best = 1e300;
-            for (int rep = 0; rep < 2 && st == PM_OK; ++rep) {
-                st = observe_time_impl<float>(c, p, 1, u, &np, &seed, obs, n_obs, kappa, T, dt, tmp,
-                                              tmp + n_obs, nullptr);
-                if (st) break;
-                if (hipStreamSynchronize(c->stream) != hipSuccess) {
-                    st = PM_EDEVICE;
-                    break;
-                }
-                float f = 0.f;
-                if (hipEventElapsedTime(&f, c->ev0, c->ev1) != hipSuccess) {
-                    st = PM_EDEVICE;
-                    break;
-                }
-                if (f < ms_best) ms_best = f;
-            }
-            if (st == PM_OK && ms_best < best) {
-                best = ms_best;
+            double ms = 0.0;
+            st = probe_ms(c, p, u, obs, n_obs, kappa, T, dt, np, seed, tmp, &ms);
+            if (st == PM_OK && ms < best) {
+                best = ms;
                 best_ppl = ppls[pi];
                 best_src = src;
             }
@@ -1597,7 +1624,6 @@ int pm_autotune_time(pm_ctx *c, const pm_problem *p, const double *u, const doub
     }
     c->ppl = save_ppl;
     c->src = save_src;
-    c->engine = save_engine;
     (void)hipFree(tmp);
     if (st) return st;
     c->tune_ppl[p->K] = best_ppl;

@@ -184,14 +184,29 @@ __device__ __forceinline__ void cheb_basis(float s, float S, float *phi)
     }
 }
 
+// Operand registers of the tile's padding rows (x-basis entries 8 + 2d,
+// 9 + 2d >= B, whose coefficient columns are zero): any finite FP16 values
+// serve there.  A caller that evaluates the velocity repeatedly keeps them
+// from one call to the next (initially zero), so the swap that moves the
+// partner's entries 2d, 2d + 1 needs no fresh zero register each time.
+struct MxPad {
+    uint32_t h[4] = {0u, 0u, 0u, 0u}, l[4] = {0u, 0u, 0u, 0u};
+};
+
 // The contraction W = A^T Phi_x for the 64 particles of a wave: x basis x 2^8
 // (px, from cheb_basis) split into FP16 pairs (P holds entries 0..7, Q
-// 8..15; entries past B are zero), the half-wave swaps that make P the B operand of
+// 8..15; entries past B are padding), the half-wave swaps that make P the B operand of
 // column block 0 (particles 0..31) and Q that of block 1 (32..63), and the three split
-// products per block.
+// products per block.  A register pair whose entries are all padding in both
+// P and Q is not swapped (zero); one whose Q entries alone are padding swaps
+// P with the carried padding register of `pad` (a swap writes the upper
+// half-wave of P and the lower half-wave of its partner, so the carried
+// register's upper half keeps its initial zero and its lower half receives
+// the partner's P entries, while P's upper half takes finite values of the
+// previous call into padding rows).
 template <int K>
 __device__ __forceinline__ void mx_contract(const h16x8 ahi, const h16x8 alo, const float *px, f32x16 &d0,
-                                            f32x16 &d1)
+                                            f32x16 &d1, MxPad &pad)
 {
     constexpr int B = 2 * K + 1 < 16 ? 2 * K + 1 : 16;  // entries in the tile
     static_assert(K >= 1 && K <= MX_MAX_K, "small-K path");
@@ -209,8 +224,17 @@ __device__ __forceinline__ void mx_contract(const h16x8 ahi, const h16x8 alo, co
     }
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
+        if (2 * d >= B) continue;  // all padding: zero in both halves, nothing to move
+        if (8 + 2 * d >= B) {      // Q padding: swap with the carried register
+            Qh[d] = pad.h[d];
+            Ql[d] = pad.l[d];
+        }
         swap_halves(Ph[d], Qh[d]);
         swap_halves(Pl[d], Ql[d]);
+        if (8 + 2 * d >= B) {
+            pad.h[d] = Qh[d];
+            pad.l[d] = Ql[d];
+        }
     }
     const h16x8 b0h = __builtin_bit_cast(h16x8, (u32x4){Ph[0], Ph[1], Ph[2], Ph[3]});
     const h16x8 b0l = __builtin_bit_cast(h16x8, (u32x4){Pl[0], Pl[1], Pl[2], Pl[3]});
@@ -236,7 +260,8 @@ __device__ __forceinline__ void mx_contract(const h16x8 ahi, const h16x8 alo, co
 //   v_c += phi_16(x) sum_{j<=16} C_c[16][j] phi_j(y) + phi_16(y) sum_{i<16} C_c[i][16] phi_i(x).
 template <int K>
 __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, float inv, float xh, float yh,
-                                            float &vx, float &vy, const float *__restrict__ border = nullptr)
+                                            float &vx, float &vy, MxPad &pad,
+                                            const float *__restrict__ border = nullptr)
 {
     constexpr int B = 2 * K + 1;
     float px[17];
@@ -244,7 +269,7 @@ __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, fl
 #pragma unroll
     for (int e = B; e < 17; ++e) px[e] = 0.f;
     f32x16 d0, d1;
-    mx_contract<K>(ahi, alo, px, d0, d1);
+    mx_contract<K>(ahi, alo, px, d0, d1, pad);
 
     // y basis (FP32, unscaled) while the matrix cores work: Py = entries 2q,
     // Qy = entries 2q + 1; after the swaps Py serves column block 0 and Qy
@@ -305,7 +330,7 @@ __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, fl
 // engine forms it.
 template <int K>
 __device__ __forceinline__ void mx_velocity_disk(const h16x8 ahi, const h16x8 alo, float inv, float xh, float yh,
-                                                 float &vx, float &vy)
+                                                 float &vx, float &vy, MxPad &pad)
 {
     constexpr int B = 2 * K + 1;
     static_assert(K >= 1 && B <= 9, "disk rows");
@@ -314,7 +339,7 @@ __device__ __forceinline__ void mx_velocity_disk(const h16x8 ahi, const h16x8 al
 #pragma unroll
     for (int e = B; e < 16; ++e) px[e] = 0.f;
     f32x16 d0, d1;
-    mx_contract<K>(ahi, alo, px, d0, d1);
+    mx_contract<K>(ahi, alo, px, d0, d1, pad);
     float py[16];
     cheb_basis<K>(yh, 1.f, py);
 #pragma unroll
@@ -455,7 +480,7 @@ __device__ __forceinline__ float set_vbound(const unsigned char *__restrict__ se
 // kernel, so the payoff and reduction kernels are shared).
 // ---------------------------------------------------------------------------
 template <int K, bool MT>
-__global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_time_mx(const MxTimeArgs m)
 {
     // K = 8: the border coefficients of the wave's parameter set, re-read from
     // LDS at every step (broadcast) rather than held in 66 registers
@@ -468,6 +493,7 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
     h16x8 ahi = {}, alo = {};
     float inv = 0.f;
     bool wide = false;
+    MxPad pad;
     for (;;) {
         unsigned long long tk = 0;
         if (lane == 0) tk = atomicAdd(a.queue, 1ull);
@@ -543,7 +569,7 @@ __global__ __launch_bounds__(256) void k_time_mx(const MxTimeArgs m)
             auto step = [&](float z0, float z1) {
                 float vx, vy;
                 if constexpr (K == 8) __asm__ volatile("" ::: "memory");  // re-read the borders every step
-                mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy, my_border);
+                mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy, pad, my_border);
                 if constexpr (WIDE) {
                     x.advance_wide(vx + a.v0x, z0, m.fx);
                     y.advance_wide(vy + a.v0y, z1, m.fx);
@@ -602,7 +628,8 @@ __global__ __launch_bounds__(256) void k_step_mx(const MxStepArgs a)
     x.set(act ? a.X[2 * e] : 0.0);
     y.set(act ? a.X[2 * e + 1] : 0.0);
     float vx, vy;
-    mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy, s_border);
+    MxPad pad;
+    mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy, pad, s_border);
     if (!act) return;
     if (a.V) {
         a.V[2 * e] = (double)(vx + a.v0x);
@@ -633,8 +660,10 @@ __global__ __launch_bounds__(256) void k_dirichlet_mx(const DirArgs<float> a, co
     h16x8 ahi, alo;
     float inv;
     load_set(set, lane, ahi, alo, inv);
-    dirichlet_walk<float, FK, PM_DISK, DiskFix>(
-        a, fx, [&](float xa, float ya, float &vx, float &vy) { mx_velocity_disk<K>(ahi, alo, inv, xa, ya, vx, vy); });
+    MxPad pad;
+    dirichlet_walk<float, FK, PM_DISK, DiskFix>(a, fx, [&](float xa, float ya, float &vx, float &vy) {
+        mx_velocity_disk<K>(ahi, alo, inv, xa, ya, vx, vy, pad);
+    });
 }
 
 // Teacher-forced steps and velocity on the disk (the walk's fixed-point
@@ -655,7 +684,8 @@ __global__ __launch_bounds__(256) void k_step_mx_disk(const MxStepArgs a)
     x.set(a.V ? 0.0 : xd);
     y.set(a.V ? 0.0 : yd);
     float vx, vy;
-    mx_velocity_disk<K>(ahi, alo, inv, a.V ? (float)xd : x.at(), a.V ? (float)yd : y.at(), vx, vy);
+    MxPad pad;
+    mx_velocity_disk<K>(ahi, alo, inv, a.V ? (float)xd : x.at(), a.V ? (float)yd : y.at(), vx, vy, pad);
     if (!act) return;
     if (a.V) {
         a.V[2 * e] = (double)(vx + a.v0x);

@@ -24,9 +24,9 @@ reads another's files unless given them):
                                                  and the pCN step beta from a
                                                  pilot of the plain chain
     chain  --model model.npz --kind plain|da|da_aem --iters N
-           --state chain.json --trace trace.npz  run N more iterations of a
-                                                 chain, resuming from --state
-                                                 when it exists
+           --state chain.json --trace trace.npz  run a chain to N iterations,
+           [--max-seconds S]                     resuming from --state when it
+                                                 exists, saving every 5,000
     report --model model.npz --trace plain=... da=...   ESS and rates (CPU)
 
 The prior draws are regenerated from the seed in every stage, so only G
@@ -143,7 +143,12 @@ def stage_train(data_files, out: str, epochs: int, lr: float, lr_final: float, p
     ctx.close()
 
 
-def stage_chain(model: str, kind: str, iters: int, state: str, trace: str, block: int = 500):
+def stage_chain(model: str, kind: str, iters: int, state: str, trace: str, block: int = 500,
+                max_seconds: float = float("inf"), save_every: int = 5000):
+    """Run the chain to `iters` iterations in total (resuming from `state`
+    when it exists), saving state and trace every `save_every` iterations and
+    stopping early, after a save, once `max_seconds` of this session have
+    passed."""
     import torch
     import paper_1808_10580_amd as pm
     from paper_1808_10580_amd import mcmc
@@ -164,18 +169,31 @@ def stage_chain(model: str, kind: str, iters: int, state: str, trace: str, block
             ck = json.load(fh)
         c = mcmc.Chain.resume(ck["chain"])
         seconds, calls = float(ck["seconds"]), int(ck["sessions"])
+        # the trace is replaced before the state, so it holds at least c.it rows
         tr = np.load(trace)
-        coords, phis = [tr["coords"]], [tr["phi"]]
+        coords, phis = [tr["coords"][:c.it]], [tr["phi"][:c.it]]
         _log(f"{kind}: resumed at iteration {c.it}")
     else:
         c = mcmc.start_chain(setup["u_star"], fwd, y, gamma, seed=SEED + 2, surrogate=surf, gamma_s=gamma_s)
         seconds, calls = 0.0, 0
         coords, phis = [], []
+    def save(chain_s):
+        ck = c.checkpoint()
+        ck["u"] = ck["u"].tolist()
+        with open(state + ".tmp", "w") as fh:
+            json.dump({"chain": ck, "seconds": chain_s, "sessions": calls + 1, "kind": kind, "beta": beta}, fh)
+        np.savez(trace + ".tmp.npz", coords=np.concatenate(coords) if coords else np.zeros((0, 8)),
+                 phi=np.concatenate(phis) if phis else np.zeros(0), seconds=chain_s, it=c.it,
+                 n_accept=c.n_accept, n_stage1=c.n_stage1, n_forward=c.n_forward)
+        os.replace(trace + ".tmp.npz", trace)
+        os.replace(state + ".tmp", state)
+        _log(f"{kind}: saved at iteration {c.it}, {chain_s:.0f} s of chain time")
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    done = 0
-    while done < iters:
-        nb = min(block, iters - done)
+    start_it = c.it
+    while c.it < iters:
+        nb = min(block, iters - c.it)
         if kind == "plain":
             mcmc.pcn_steps(c, nb, fwd, prior_std, y, gamma, beta)
         else:
@@ -185,21 +203,16 @@ def stage_chain(model: str, kind: str, iters: int, state: str, trace: str, block
         phis.append(np.array(c.phis))
         c.samples.clear()
         c.phis.clear()
-        done += nb
-        if done % 2500 == 0 or done == iters:
-            el = time.perf_counter() - t0
-            _log(f"{kind}: iteration {c.it} ({done}/{iters} this session, {el:.0f} s, "
-                 f"{done / el:.1f}/s, accepted {c.n_accept}, particle maps {c.n_forward})")
-    torch.cuda.synchronize()
-    seconds += time.perf_counter() - t0
-    ck = c.checkpoint()
-    ck["u"] = ck["u"].tolist()
-    with open(state + ".tmp", "w") as fh:
-        json.dump({"chain": ck, "seconds": seconds, "sessions": calls + 1, "kind": kind, "beta": beta}, fh)
-    os.replace(state + ".tmp", state)
-    np.savez(trace, coords=np.concatenate(coords), phi=np.concatenate(phis), seconds=seconds, it=c.it,
-             n_accept=c.n_accept, n_stage1=c.n_stage1, n_forward=c.n_forward)
-    _log(f"{kind}: saved at iteration {c.it}, {seconds:.0f} s of chain time")
+        el = time.perf_counter() - t0
+        if c.it % 2500 == 0 or c.it == iters:
+            done = c.it - start_it
+            _log(f"{kind}: iteration {c.it} ({done} this session, {el:.0f} s, {done / el:.1f}/s, "
+                 f"accepted {c.n_accept}, particle maps {c.n_forward})")
+        if c.it % save_every == 0 or c.it == iters or el > max_seconds:
+            torch.cuda.synchronize()
+            save(seconds + time.perf_counter() - t0)
+            if el > max_seconds:
+                break
     prob.close()
     ctx.close()
 
@@ -248,13 +261,14 @@ def main():
     ap.add_argument("--iters", type=int, default=1000)
     ap.add_argument("--state", default=None)
     ap.add_argument("--trace", nargs="*", default=[])
+    ap.add_argument("--max-seconds", type=float, default=float("inf"))
     a = ap.parse_args()
     if a.stage == "data":
         stage_data(a.part, a.n_parts, a.out, a.n_train, a.particles)
     elif a.stage == "train":
         stage_train(a.data, a.out, a.epochs, a.lr, a.lr_final)
     elif a.stage == "chain":
-        stage_chain(a.model, a.kind, a.iters, a.state, a.trace[0])
+        stage_chain(a.model, a.kind, a.iters, a.state, a.trace[0], max_seconds=a.max_seconds)
     else:
         print(json.dumps(report(a.model, dict(t.split("=", 1) for t in a.trace))))
     return 0

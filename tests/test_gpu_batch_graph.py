@@ -112,6 +112,21 @@ def test_autotune_picks_a_variant_and_keeps_results(pm, ctx, engine_of):
     ctx.set_blocks_per_cu(0)
 
 
+def test_autotune_matrix_core_engine_keeps_results(pm, ctx, engine_of):
+    """On the default matrix-core engine the autotuner picks the persistent
+    grid (blocks per compute unit); the map is bitwise the same with it."""
+    engine_of("auto")
+    wl = W.time_main()
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+    m0, v0 = prob.observe_time(wl.u, wl.obs, wl.kappa, 0.05, wl.dt, 5000, wl.seed)
+    m0, v0 = np_(m0).copy(), np_(v0).copy()
+    t = prob.autotune_time(wl.u, wl.obs, wl.kappa, wl.dt, 20000, n_probe_steps=20)
+    print("autotune (matrix cores):", t)
+    assert 1 <= t["blocks_per_cu"] <= 8 and t["probe_ms"] > 0
+    m1, v1 = prob.observe_time(wl.u, wl.obs, wl.kappa, 0.05, wl.dt, 5000, wl.seed)
+    assert np.array_equal(np_(m1), m0) and np.array_equal(np_(v1), v0)
+
+
 def test_full_batch_workload_shape(pm, ctx):
     """The 512-set batch workload (per-u particle counts log-uniform in
     [1e3, 1e5]) in one persistent launch, shortened to 20 steps: every set's

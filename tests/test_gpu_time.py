@@ -80,6 +80,23 @@ def theta0_numpy(fd, X):
                 for ny in (-1, 0, 1):
                     out += A * np.exp(-((x - cx - nx) ** 2 + (y - cy - ny) ** 2) / (2 * s * s))
         return out
+    if fd["kind"] == "fourier":
+        out = np.zeros_like(x)
+        for m in range(0, len(p), 4):
+            ph = 2 * np.pi * (p[m] * x + p[m + 1] * y)
+            out += p[m + 2] * np.cos(ph) + p[m + 3] * np.sin(ph)
+        return out
+    if fd["kind"] == "gauss":
+        out = np.zeros_like(x)
+        for m in range(0, len(p), 4):
+            out += p[m + 3] * np.exp(-p[m + 2] * ((x - p[m]) ** 2 + (y - p[m + 1]) ** 2))
+        return out
+    if fd["kind"] == "linear":
+        return p[0] * x + p[1] * y + p[2]
+    if fd["kind"] == "cos_axes":
+        return p[0] * (np.cos(p[1] * x) + np.cos(p[1] * y))
+    if fd["kind"] == "exp_linear":
+        return np.exp(p[0] * x + p[1] * y)
     raise NotImplementedError(fd["kind"])
 
 
@@ -457,6 +474,43 @@ def test_empty_mode_table_is_pure_diffusion(pm, ctx, orc):
     pay, ep_ref = orc.observe_time_payoffs(np.zeros((0, 2), np.int32), np.zeros(0), W.fld("sinsin", [1.0]), obs,
                                            0.05, 0.1, 1e-3, 300, 4, endpoints=True)
     assert np.max(tdist(np_(ep), ep_ref)) <= 1e-12
+
+
+THETA0_KINDS = {
+    "fourier": W.fld("fourier", [1, 0, 0.3, -0.2, 1, 2, 0.1, 0.4]),
+    "gauss": W.fld("gauss", [0.4, 0.6, 8.0, 1.5]),
+    "linear": W.fld("linear", [0.5, -0.25, 0.1]),
+    "cos_axes": W.fld("cos_axes", [0.5, 2.0]),
+    "exp_linear": W.fld("exp_linear", [0.3, -0.7]),
+}
+
+
+@pytest.mark.parametrize("kind", list(THETA0_KINDS))
+@pytest.mark.parametrize("prec,engine", [("fp64", "auto"), ("fp32", "valu"), ("fp32", "mfma")])
+def test_theta0_kinds_against_oracle(pm, ctx, orc, engine_of, kind, prec, engine):
+    """Initial conditions of other kinds: the means are those of theta0 (a
+    test-side formula) at the GPU's own endpoints, the endpoints follow the
+    oracle's paths, and in FP64 the means equal the oracle's to 1e-12."""
+    engine_of(engine)
+    wl = W.time_small()
+    th = THETA0_KINDS[kind]
+    Np = 130
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=th, prec=prec)
+    m, v, ep = prob.observe_time(wl.u, wl.obs, wl.kappa, wl.T, wl.dt, Np, wl.seed, endpoints=True)
+    pay, ep_ref = orc.observe_time_payoffs(wl.modes, wl.u, th, wl.obs, wl.kappa, wl.T, wl.dt, Np, wl.seed,
+                                           endpoints=True)
+    mr, vr = orc.mean_var(pay)
+    # the payoff route: the means are those of theta0 at the GPU's own endpoints
+    e_gpu = theta0_numpy(th, np_(ep))
+    assert np.max(np.abs(np_(m) - e_gpu.mean(axis=1))) <= 1e-12 * (1.0 + np.max(np.abs(e_gpu)))
+    assert np.max(np.abs(np_(v) - e_gpu.var(axis=1, ddof=1))) <= 1e-12 * (1.0 + np.max(e_gpu ** 2))
+    if prec == "fp64":
+        assert np.max(tdist(np_(ep), ep_ref)) <= 1e-12
+        assert np.max(np.abs(np_(m) - mr)) <= 1e-12
+        assert np.max(np.abs(np_(v) - vr)) <= 1e-12 * max(np.max(vr), 1e-300) + 1e-300
+    else:
+        assert np.quantile(np.max(tdist(np_(ep), ep_ref), axis=-1), 0.99) <= 1e-5
+    assert ctx.sync() == pm.PM_OK
 
 
 def test_invalid_arguments_raise(pm, ctx):
