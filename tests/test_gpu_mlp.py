@@ -89,6 +89,36 @@ def test_gradients_match_oracle(pm, ctx, dims, n):
     net.close()
 
 
+@pytest.mark.parametrize("dims,n", [(TINY, 7), (TINY, 130), (FULL, 1), (FULL, 300), (FULL, 1024)])
+def test_forward_matches_oracle_elementwise(pm, ctx, dims, n):
+    """Every output entry within its BF16 tolerance (16 u times the entry's
+    natural magnitude, tests/mlp_bounds.py)."""
+    from tests import mlp_bounds as mb
+    net, p, x, t, scale, mu, sd = _setup(pm, ctx, dims, n, 5)
+    y = net.forward(x).cpu().numpy().astype(np.float64)
+    ref = orc_mlp.predict(p, dims, x, scale, mu, sd)
+    tol = mb.forward_bounds(p, dims, x, scale, mu, sd)
+    r = np.abs(y - ref) / tol
+    print("forward %s n=%d: max error / tolerance %.3f" % (dims, n, r.max()))
+    assert np.all(r <= 1.0), (np.unravel_index(np.argmax(r), r.shape), r.max())
+    net.close()
+
+
+@pytest.mark.parametrize("dims,n", [(TINY, 33), (FULL, 64), (FULL, 256)])
+def test_gradients_match_oracle_elementwise(pm, ctx, dims, n):
+    """Every gradient entry (all weights and biases) within its BF16
+    tolerance (tests/mlp_bounds.py)."""
+    from tests import mlp_bounds as mb
+    net, p, x, t, scale, mu, sd = _setup(pm, ctx, dims, n, 6)
+    g = net.grads(x, t).astype(np.float64)
+    _, ref = orc_mlp.loss_and_grads(p, dims, x, t, scale, mu, sd)
+    tol = mb.gradient_bounds(p, dims, x, t, scale, mu, sd)
+    r = np.abs(g - ref) / tol
+    print("gradients %s n=%d: max error / tolerance %.3f at entry %d" % (dims, n, r.max(), int(np.argmax(r))))
+    assert np.all(r <= 1.0), (int(np.argmax(r)), r.max())
+    net.close()
+
+
 def test_adam_first_step_moves_each_weight_by_lr_against_its_gradient(pm, ctx):
     dims, n, lr = FULL, 256, 1e-3
     net, p, x, t, scale, mu, sd = _setup(pm, ctx, dims, n, 5)

@@ -23,6 +23,7 @@ re-deriving its update:
       to the minimum.
 """
 import numpy as np
+import pytest
 from scipy.stats import norm
 
 from oracle import mlp
@@ -126,3 +127,63 @@ def test_A6_quadratic():
     path = _run_adam(lambda p, t: h * p, p0, 4000, 1e-2)
     assert np.allclose(path[1] - p0, -1e-2 * np.sign(h * p0), rtol=1e-6)
     assert np.all(np.abs(path[-1]) < 2e-2)
+
+
+# ---------------------------------------------------------------------------
+# The element-wise BF16 tolerances that the GPU tests apply (tests/mlp_bounds.py)
+# ---------------------------------------------------------------------------
+
+def _bounds_case(dims, n, seed):
+    rng = np.random.default_rng(seed)
+    p = mlp.init_params(dims, seed) + 0.02 * rng.standard_normal(mlp.n_params(*dims))
+    x = rng.standard_normal((n, dims[0]))
+    t = rng.standard_normal((n, dims[3]))
+    scale = rng.uniform(0.5, 2.0, dims[0])
+    mu, sd = rng.standard_normal(dims[3]), rng.uniform(0.5, 2.0, dims[3])
+    return p, x, t, scale, mu, sd
+
+
+@pytest.mark.parametrize("dims,n", [((8, 16, 2, 4), 50), ((168, 512, 3, 49), 64)])
+def test_bf16_tolerances_cover_an_emulation_of_the_rounding(dims, n):
+    """The GPU's rounding sequence emulated in numpy stays within 3/4 of the
+    element-wise tolerances, forward and backward, and uses a visible part of
+    them (they are not vacuous)."""
+    from tests import mlp_bounds as mb
+    p, x, t, scale, mu, sd = _bounds_case(dims, n, 11)
+    ref = mlp.predict(p, dims, x, scale, mu, sd)
+    E = mb.forward_bounds(p, dims, x, scale, mu, sd)
+    r = np.abs(mb.emulate_forward(p, dims, x, scale, mu, sd).astype(np.float64) - ref) / E
+    assert np.all(r <= 0.75) and r.max() > 0.02, r.max()
+    _, g = mlp.loss_and_grads(p, dims, x, t, scale, mu, sd)
+    Eg = mb.gradient_bounds(p, dims, x, t, scale, mu, sd)
+    rg = np.abs(mb.emulate_grads(p, dims, x, t, scale, mu, sd) - g) / Eg
+    assert np.all(rg <= 0.75) and rg.max() > 0.02, rg.max()
+
+
+def test_bf16_tolerances_catch_plausible_kernel_mistakes():
+    """A square hidden weight used transposed, or a bias added to the wrong
+    column, breaks the element-wise forward tolerance; inputs paired with the
+    wrong rows, or output-bias gradients in the wrong order, break the
+    backward one."""
+    from tests import mlp_bounds as mb
+    dims = (8, 16, 2, 4)
+    p, x, t, scale, mu, sd = _bounds_case(dims, 50, 12)
+    E = mb.forward_bounds(p, dims, x, scale, mu, sd)
+    ref = mlp.predict(p, dims, x, scale, mu, sd)
+    off = 8 * 16 + 16
+    bad = p.copy()
+    bad[off:off + 256] = p[off:off + 256].reshape(16, 16).T.ravel()
+    assert np.any(np.abs(mb.emulate_forward(bad, dims, x, scale, mu, sd) - ref) > E)
+    bad = p.copy()
+    bb = off + 256
+    bad[bb:bb + 16] = np.roll(p[bb:bb + 16], 1)
+    assert np.any(np.abs(mb.emulate_forward(bad, dims, x, scale, mu, sd) - ref) > E)
+    _, g = mlp.loss_and_grads(p, dims, x, t, scale, mu, sd)
+    Eg = mb.gradient_bounds(p, dims, x, t, scale, mu, sd)
+    # inputs paired with the wrong targets (rows off by one)
+    _, g_wrong = mlp.loss_and_grads(p, dims, np.roll(x, 1, axis=0), t, scale, mu, sd)
+    assert np.any(np.abs(g_wrong - g) > Eg)
+    # the bias gradient of the output layer left out of the flat vector order
+    _, g_wrong = mlp.loss_and_grads(p, dims, x, t, scale, mu, sd)
+    g_wrong[-4:] = np.roll(g_wrong[-4:], 1)
+    assert np.any(np.abs(g_wrong - g) > Eg)
