@@ -97,7 +97,11 @@ def _forward(pm, ctx, wl):
     return prob, mcmc.ParticleForward(prob, wl, CHAIN_PARTICLES, wl.seed)
 
 
-def stage_train(data_files, out: str, epochs: int, lr: float, lr_final: float, pilot: int = 60):
+def stage_train(data_files, out: str, epochs: int, lr: float, lr_final: float, pilot: int = 60,
+                reuse: str = None, early_stop: bool = False):
+    """Fit the network; then G(u*), y and the pCN step from a pilot, or (reuse)
+    take y, G(u*), gamma and beta from an earlier model file, so that chains
+    started with either model sample the same posterior."""
     import paper_1808_10580_amd as pm
     from paper_1808_10580_amd import mcmc
     from paper_1808_10580_amd.surrogate import Surrogate
@@ -111,23 +115,28 @@ def stage_train(data_files, out: str, epochs: int, lr: float, lr_final: float, p
     _log(f"training on {U.shape[0]} pairs")
     ctx = pm.Context(0)
     sur = Surrogate(ctx, prior_std, wl.n_obs, seed=SEED)
-    hist = sur.fit(U, G, epochs=epochs, batch=1024, lr=lr, lr_final=lr_final,
+    hist = sur.fit(U, G, epochs=epochs, batch=1024, lr=lr, lr_final=lr_final, early_stop=early_stop,
                    progress=lambda ep, v: _log(f"epoch {ep}: held-out rmse {v:.4f} (std units)")
-                   if ep % 10 == 0 or ep == epochs - 1 else None)
-    _log(f"trained in {hist['seconds']:.1f} s, {hist['steps']} steps")
+                   if ep % 10 == 0 or ep == epochs - 1 or early_stop else None)
+    _log(f"trained in {hist['seconds']:.1f} s, {hist['steps']} steps, kept epoch {hist.get('best_epoch', epochs - 1)}")
     prob, fwd = _forward(pm, ctx, wl)
-    g_star = fwd(setup["u_star"])
-    gamma = setup["gamma"]
-    y = g_star + gamma * setup["eta"]
-    # pCN step for a plain-chain acceptance rate in [0.15, 0.4] (short pilot)
-    beta, acc = 0.02, 0.0
-    for _ in range(6):
-        pc = mcmc.start_chain(setup["u_star"], fwd, y, gamma, seed=SEED + 1)
-        mcmc.pcn_steps(pc, pilot, fwd, prior_std, y, gamma, beta)
-        acc = pc.n_accept / pilot
-        if 0.15 <= acc <= 0.4:
-            break
-        beta *= 2.0 if acc > 0.4 else 0.5
+    if reuse:
+        old = np.load(reuse)
+        y, g_star, gamma, beta, acc = (old["y"], old["g_star"], float(old["gamma"]), float(old["beta"]),
+                                       float(old["pilot_accept"]))
+    else:
+        g_star = fwd(setup["u_star"])
+        gamma = setup["gamma"]
+        y = g_star + gamma * setup["eta"]
+        # pCN step for a plain-chain acceptance rate in [0.15, 0.4] (short pilot)
+        beta, acc = 0.02, 0.0
+        for _ in range(6):
+            pc = mcmc.start_chain(setup["u_star"], fwd, y, gamma, seed=SEED + 1)
+            mcmc.pcn_steps(pc, pilot, fwd, prior_std, y, gamma, beta)
+            acc = pc.n_accept / pilot
+            if 0.15 <= acc <= 0.4:
+                break
+            beta *= 2.0 if acc > 0.4 else 0.5
     _log(f"pilot: beta {beta}, acceptance {acc:.2f}")
     val = hist["val_idx"]
     pv = sur.predict(U[val])
@@ -137,7 +146,7 @@ def stage_train(data_files, out: str, epochs: int, lr: float, lr_final: float, p
              val_rmse_std=hist["val_rmse"][-1], val_rmse_hist=np.array(hist["val_rmse"]),
              err_at_ustar=float(np.sqrt(np.mean((sur(setup["u_star"]) - g_star) ** 2))),
              train_s=hist["seconds"], train_steps=hist["steps"], data_s=data_s, n_train=U.shape[0],
-             epochs=epochs, lr=lr, lr_final=lr_final)
+             epochs=epochs, lr=lr, lr_final=lr_final, best_epoch=hist.get("best_epoch", epochs - 1))
     _log(f"held-out rmse of G {float(np.sqrt(np.mean((pv - G[val]) ** 2))):.4f}; saved {out}")
     prob.close()
     ctx.close()
@@ -257,6 +266,8 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--lr-final", type=float, default=5e-5)
     ap.add_argument("--model", default=None)
+    ap.add_argument("--reuse", default=None, help="train: take y, G(u*), gamma, beta from this model file")
+    ap.add_argument("--early-stop", action="store_true", help="train: keep the epoch with the lowest held-out error")
     ap.add_argument("--kind", default="plain", choices=["plain", "da", "da_aem"])
     ap.add_argument("--iters", type=int, default=1000)
     ap.add_argument("--state", default=None)
@@ -266,7 +277,7 @@ def main():
     if a.stage == "data":
         stage_data(a.part, a.n_parts, a.out, a.n_train, a.particles)
     elif a.stage == "train":
-        stage_train(a.data, a.out, a.epochs, a.lr, a.lr_final)
+        stage_train(a.data, a.out, a.epochs, a.lr, a.lr_final, reuse=a.reuse, early_stop=a.early_stop)
     elif a.stage == "chain":
         stage_chain(a.model, a.kind, a.iters, a.state, a.trace[0], max_seconds=a.max_seconds)
     else:

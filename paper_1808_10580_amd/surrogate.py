@@ -44,10 +44,13 @@ class Surrogate:
         self.max_batch = max_batch
 
     def fit(self, U: np.ndarray, G: np.ndarray, epochs: int = 20, batch: int = 1024, lr: float = 1e-3,
-            holdout: float = 0.1, seed: int = 0, lr_final: Optional[float] = None, progress=None) -> Dict:
+            holdout: float = 0.1, seed: int = 0, lr_final: Optional[float] = None, progress=None,
+            early_stop: bool = False) -> Dict:
         """Adam on the standardised MSE; the learning rate decays geometrically
         from lr to lr_final over the epochs when lr_final is given.
-        progress(epoch, val_rmse) is called after each epoch when given."""
+        progress(epoch, val_rmse) is called after each epoch when given.
+        early_stop: keep the parameters of the epoch with the lowest held-out
+        error (the held-out rows are then also the selection set)."""
         import torch
         rng = np.random.default_rng(seed)
         n = U.shape[0]
@@ -76,8 +79,13 @@ class Surrogate:
             hist["train"].append(float(torch.stack(losses).mean().item()) if losses else float("nan"))
             pv = self.predict(U[val])
             hist["val_rmse"].append(float(np.sqrt(np.mean(((pv - G[val]) / sd) ** 2))))
+            if early_stop and hist["val_rmse"][-1] <= min(hist["val_rmse"]):
+                best = (ep, self.net.get_params())
             if progress is not None:
                 progress(ep, hist["val_rmse"][-1])
+        if early_stop and epochs > 0:
+            hist["best_epoch"] = best[0]
+            self.net.set_params(best[1])  # also resets the Adam moments
         torch.cuda.synchronize()
         hist["seconds"] = time.perf_counter() - t0
         hist["val_idx"] = val
