@@ -477,6 +477,57 @@ def disk_tail_bound(pm, ctx, prob, wl, u, obs, map_s):
             "lone_walk_ns_per_step": round(lone_ms * 1e6 / max(n_max, 1), 2)}
 
 
+def bench_pcn(args):
+    """pCN samples/s on the main map, plain against delayed acceptance with a
+    trained surrogate (a model file of `python -m paper_1808_10580_amd.da_prior
+    train`), both with the particle map at 1e5 particles deciding acceptance;
+    ESS of the misfit and of the first 8 coefficients (Geyer) per second,
+    the equal-error comparison.  --steps is the number of chain iterations."""
+    import numpy as np
+    import torch
+    import paper_1808_10580_amd as pm
+    from paper_1808_10580_amd import da_prior, mcmc
+    from paper_1808_10580_amd.surrogate import Surrogate
+
+    if not args.model:
+        print("--workload pcn needs --model (a da_prior train output)", file=sys.stderr)
+        sys.exit(2)
+    _, setup, wl, prior_std = da_prior._setup()
+    md = np.load(args.model)
+    y, gamma, beta = md["y"], float(md["gamma"]), float(md["beta"])
+    ctx = pm.Context(0)
+    prob = pm.Problem(ctx, "torus", wl.modes, theta0=wl.theta0, prec="fp32")
+    fwd = mcmc.ParticleForward(prob, wl, da_prior.CHAIN_PARTICLES, wl.seed)
+    sur = Surrogate(ctx, prior_std, wl.n_obs, seed=da_prior.SEED).load(md)
+    res = {}
+    for kind in ("plain", "da"):
+        c = mcmc.start_chain(setup["u_star"], fwd, y, gamma, seed=da_prior.SEED + 2,
+                             surrogate=sur if kind == "da" else None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if kind == "plain":
+            mcmc.pcn_steps(c, args.steps, fwd, prior_std, y, gamma, beta)
+        else:
+            mcmc.da_pcn_steps(c, args.steps, fwd, sur, prior_std, y, gamma, beta)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        S = np.array(c.samples)
+        e8 = mcmc.ess_min(S, range(8))
+        ephi = mcmc.ess(np.array(c.phis))
+        res[kind] = {"samples_per_s": args.steps / sec, "particle_map_calls": c.n_forward,
+                     "accept_rate": c.n_accept / args.steps, "ess_phi_per_s": ephi / sec,
+                     "ess_min_first8_per_s": e8 / sec}
+    out = {"metric": "pCN samples/s, surrogate vs plain at equal error", "value": res["da"]["samples_per_s"],
+           "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": 0, "higher_is_better": True,
+           "vs_baseline": None, "data": "synthetic",
+           "config": {"workload": "torus-k6-fp32 posterior: y = G(u*) + N(0, 0.01^2), 1e5-particle map, pCN beta "
+                                  f"{beta}, surrogate {args.model}"},
+           "plain": res["plain"], "delayed_acceptance": res["da"],
+           "da_vs_plain": {"samples_per_s": res["da"]["samples_per_s"] / res["plain"]["samples_per_s"],
+                           "ess_phi_per_s": res["da"]["ess_phi_per_s"] / max(res["plain"]["ess_phi_per_s"], 1e-300)}}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -489,6 +540,7 @@ def main():
     ap.add_argument("--coef-source", type=int, default=0, help="0 = LDS, 1 = scalar cache")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the (untimed) kernel-variant autotuning before the timed steps")
+    ap.add_argument("--model", default=None, help="pcn workload: a surrogate model file (da_prior train)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 512-set batched map reported beside the main line")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -498,7 +550,7 @@ def main():
                     help="velocity engine of FP32 problems (auto = matrix cores for torus K <= 8, disk K <= 4)")
     ap.add_argument("--workload", default="torus-k6-fp32",
                     help="torus-k6-fp32 (the benchmark line), torus-k80-turbulent, disk-dirichlet, torus-k6-batch, "
-                         "torus-modes-sweep")
+                         "torus-modes-sweep, pcn (with --model)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -508,6 +560,9 @@ def main():
         sys.exit(2)
     if args.workload == "torus-modes-sweep":
         bench_modes_sweep(args)
+        return
+    if args.workload == "pcn":
+        bench_pcn(args)
         return
     if args.workload != "torus-k6-fp32":
         bench_other(args)
@@ -570,6 +625,7 @@ def main():
     elif engine == "valu":
         roofline["variant"] = {"particles_per_lane": args.ppl or 2, "coef_source": args.coef_source}
     batch = None if args.no_batch else measure_batch(pm, ctx, W, args)
+    pcn = None if args.no_batch else measure_pcn_plain(pm, ctx, prob, wl)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -598,7 +654,34 @@ def main():
     }
     if batch is not None:
         out["batch"] = batch
+    if pcn is not None:
+        out["pcn_plain"] = pcn
     print(json.dumps(out))
+
+
+def measure_pcn_plain(pm, ctx, prob, wl, iters: int = 40):
+    """Plain pCN on this map (Section 4.1's sampler; data y = G(u*) + N(0,
+    0.01^2) from a seeded prior draw u*): one captured forward map per
+    iteration, u written into it, the 49 means back on the host for the
+    accept test.  Samples/s over `iters` iterations after one untimed."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1808_10580_amd import mcmc
+    setup = W.surrogate_setup()
+    std = W.prior_std(wl.modes)
+    prior_std = np.concatenate([std, std])
+    fwd = mcmc.ParticleForward(prob, wl, wl.n_particles, wl.seed)
+    y = fwd(setup["u_star"]) + setup["gamma"] * setup["eta"]
+    c = mcmc.start_chain(setup["u_star"], fwd, y, setup["gamma"], seed=1)
+    mcmc.pcn_steps(c, 1, fwd, prior_std, y, setup["gamma"], 0.04)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mcmc.pcn_steps(c, iters, fwd, prior_std, y, setup["gamma"], 0.04)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    return {"samples_per_s": iters / sec, "iterations": iters, "beta": 0.04,
+            "note": "plain pCN; the surrogate comparison at equal error: bench.py --workload pcn --model ..."}
 
 
 def measure_batch(pm, ctx, W, args):

@@ -143,7 +143,8 @@ def stage_train(data_files, out: str, epochs: int, lr: float, lr_final: float, p
     st = sur.state()
     np.savez(out, **st, y=y, g_star=g_star, gamma=gamma, beta=beta, pilot_accept=acc,
              val_rmse_G=float(np.sqrt(np.mean((pv - G[val]) ** 2))),
-             val_rmse_std=hist["val_rmse"][-1], val_rmse_hist=np.array(hist["val_rmse"]),
+             val_rmse_std=hist["val_rmse"][hist.get("best_epoch", epochs - 1)],
+             val_rmse_hist=np.array(hist["val_rmse"]),
              err_at_ustar=float(np.sqrt(np.mean((sur(setup["u_star"]) - g_star) ** 2))),
              train_s=hist["seconds"], train_steps=hist["steps"], data_s=data_s, n_train=U.shape[0],
              epochs=epochs, lr=lr, lr_final=lr_final, best_epoch=hist.get("best_epoch", epochs - 1))
@@ -232,7 +233,8 @@ def report(model: str, traces: dict) -> dict:
     from paper_1808_10580_amd import mcmc
     md = np.load(model)
     out = {"n_train": int(md["n_train"]), "train_s": float(md["train_s"]), "data_s": float(md["data_s"]),
-           "val_rmse_G": float(md["val_rmse_G"]), "val_rmse_std": float(md["val_rmse_std"]),
+           "val_rmse_G": float(md["val_rmse_G"]),
+           "val_rmse_std": float(np.min(md["val_rmse_hist"])) if "best_epoch" in md else float(md["val_rmse_std"]),
            "err_at_ustar": float(md["err_at_ustar"]), "gamma": float(md["gamma"]), "beta": float(md["beta"]),
            "surrogate_err_std_mean": float(np.mean(md["err_std"]))}
     for kind, path in traces.items():
