@@ -14,7 +14,9 @@ namespace pm {
 // ---------------------------------------------------------------------------
 constexpr int MX_MAX_K = 8;
 constexpr int MX_MAX_K_DISK = 4;         // the disk's three forms: 3 x 9 rows of the 32-row tile
-constexpr int MX_BASIS_SHIFT = 8;        // the x basis enters the products scaled by 2^8
+// Power-of-two scale of the x basis in the products (0: unscaled; the matrix
+// cores take FP16 subnormal low halves exactly).
+constexpr int MX_BASIS_SHIFT = 0;
 // Per parameter set: 64-byte header, A hi, A lo (64 lanes x 16 B each), then
 // MX_BORDER_FLOATS border coefficients (K = 8): C_c[16][j] for c = x, y and
 // j = 0..16, then C_c[i][16] x 2^-MX_BASIS_SHIFT for i = 0..15.

@@ -13,10 +13,14 @@
 // (32 rows: 16 per component, B <= 16 x-basis functions, 64 particles) on
 // v_mfma_f32_32x32x16_f16.  Operands are split into FP16 pairs (a = a_hi +
 // a_lo) and three products a_hi b_hi + a_hi b_lo + a_lo b_hi are accumulated
-// in FP32: about 2^-22 relative error per product.  The x basis enters
-// scaled by 2^8 and the coefficients by a power of two that puts max |C| in
-// [2^14, 2^15), so the low halves stay normal FP16 numbers; the result is
-// scaled back exactly.
+// in FP32: about 2^-22 relative error per product.  The coefficients enter
+// scaled by a power of two that puts max |C| in [2^14, 2^15), so their low
+// halves stay normal FP16 numbers, and the result is scaled back exactly.
+// The x basis enters unscaled: the low halves of entries below 2^-3 are FP16
+// subnormals, which the matrix cores take exactly (an in-bounds product of
+// subnormal operands on gfx950 equals the exact sum), so such an entry keeps
+// an absolute resolution of 2^-25, below the relative error of the split
+// products.
 //
 // Matrix-core layouts (32x32x16, lane l, h = l / 32):
 //   A (32 rows x 16 cols i): lane l holds row l % 32, cols i = 8 h + e (e = 0..7);
@@ -193,7 +197,7 @@ struct MxPad {
     uint32_t h[4] = {0u, 0u, 0u, 0u}, l[4] = {0u, 0u, 0u, 0u};
 };
 
-// The contraction W = A^T Phi_x for the 64 particles of a wave: x basis x 2^8
+// The contraction W = A^T Phi_x for the 64 particles of a wave: x basis
 // (px, from cheb_basis) split into FP16 pairs (P holds entries 0..7, Q
 // 8..15; entries past B are padding), the half-wave swaps that make P the B operand of
 // column block 0 (particles 0..31) and Q that of block 1 (32..63), and the three split
@@ -314,7 +318,7 @@ __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, fl
             s0 = __builtin_fmaf(border[34 + i], px[i], s0);
             s1 = __builtin_fmaf(border[50 + i], px[i], s1);
         }
-        const float p16 = px[16] * 0x1p-8f;  // phi_16(x), exact
+        const float p16 = px[16] * (1.0f / (float)(1 << MX_BASIS_SHIFT));  // phi_16(x), exact
         vx = __builtin_fmaf(r0, p16, __builtin_fmaf(s0, py[16], vx));
         vy = __builtin_fmaf(r1, p16, __builtin_fmaf(s1, py[16], vy));
     }

@@ -133,11 +133,17 @@ def test_batch_workload_full_horizon_against_oracle_subsample(pm, ctx, orc):
     n_or = 256
     zs = []
     for b in (0, 7, 255, 511):
-        mr, vr = orc.observe_time(wl.modes, wl.u[b], wl.theta0, wl.obs, wl.kappa, wl.T, wl.dt, n_or,
-                                  int(wl.seed[b]))
+        pay = orc.observe_time_payoffs(wl.modes, wl.u[b], wl.theta0, wl.obs, wl.kappa, wl.T, wl.dt, n_or,
+                                       int(wl.seed[b]))
+        mr, vr = orc.mean_var(pay)
         se = np.sqrt(vr / n_or + vb[b] / wl.n_particles[b])
         zs.append(np.abs(mb[b] - mr) / se)
-        assert np.all(np.abs(vb[b] - vr) <= 6 * vr * math.sqrt(2 / n_or) + 1e-12), b
+        # the variances: standard error of a sample variance from the fourth
+        # central moment (the payoffs are far from normal: most particles
+        # miss the bumps), estimated on the oracle's sample for both sides
+        m4 = np.mean((pay - mr[:, None]) ** 4, axis=1)
+        se_v = np.sqrt(np.maximum(m4 - vr ** 2, 0) * (1.0 / n_or + 1.0 / wl.n_particles[b]))
+        assert np.all(np.abs(vb[b] - vr) <= 5 * se_v + 1e-12), (b, np.max(np.abs(vb[b] - vr) / se_v))
     z = np.concatenate(zs)
     print("512-set batch, T = 1: sets 0/7/255/511 (N_p %s) against 256 oracle particles per point: "
           "z max %.2f, %d of %d above 3" % (list(wl.n_particles[[0, 7, 255, 511]]), z.max(), np.sum(z > 3), z.size))
