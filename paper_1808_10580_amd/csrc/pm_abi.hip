@@ -617,6 +617,7 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
             MxTimeArgs ma{};
             ma.t = a;
             ma.fx = fixed_consts(dte, kappa);
+            ma.gauss = (float)(-2.0 * std::log(2.0) * (2.0 * kappa * dte) * 0x1p64);
             ma.sets = mx_sets;
             ma.vmax_fast = (float)((0.45 - 5.9 * std::sqrt(2.0 * kappa * dte)) / dte -
                                    std::max(std::fabs(p->v0[0]), std::fabs(p->v0[1])));

@@ -65,18 +65,34 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
 // product of the second and third rounds that they feed are uniform as
 // well: those exclusive ors are plain ones, which the compiler places on the
 // scalar unit together with the products (the three-input vector form would
-// pull them onto the vector units).  Bitwise the same words as philox4x32_10.
+// pull them onto the vector units).  Where two of the three inputs of an
+// exclusive or are uniform and one is not (rounds 1-3), the uniform pair is
+// combined on the scalar unit first (`su`): a vector instruction reads one
+// scalar operand, so the three-input form would copy the second one into a
+// vector register.  Round 0's new word 0 does not depend on c0 (the step
+// block) and keeps the form the compiler hoists out of a step loop.
+// Bitwise the same words as philox4x32_10.
 __device__ __forceinline__ U4 philox4x32_10_wu(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t k0, uint32_t k1)
 {
     uint32_t c3 = 0u;
+    auto su = [](uint32_t a, uint32_t b) { return __builtin_amdgcn_readfirstlane(a ^ b); };
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
         const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
         const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-        const uint32_t n0 = r == 1 ? hi1 ^ c1 ^ k0 : __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
-        const uint32_t n2 = r == 0 ? hi0 ^ c3 ^ k1 : __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
+        // uniform words entering round r: r = 0: all but c1; r = 1: c1, c2,
+        // c3; r = 2: c0, c1, c3; r = 3: c3 (k0, k1 always)
+        uint32_t n0, n2;
+        if (r == 0) n0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);  // no step index: hoisted
+        else if (r == 1) n0 = hi1 ^ c1 ^ k0;
+        else if (r == 2) n0 = hi1 ^ su(c1, k0);
+        else n0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
+        if (r == 0) n2 = hi0 ^ c3 ^ k1;
+        else if (r == 1 || r == 3) n2 = hi0 ^ su(c3, k1);
+        else if (r == 2) n2 = c3 ^ su(hi0, k1);
+        else n2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
         c0 = n0;
         c1 = lo1;
         c2 = n2;
@@ -95,6 +111,17 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float &z0, 
     const float ua = __builtin_fmaf((float)(wa >> 8), 0x1p-24f, 0x1p-24f);
     const float ub = (float)(wb >> 8) * 0x1p-24f;
     const float r = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(ua));
+    z0 = r * __builtin_amdgcn_cosf(ub);
+    z1 = r * __builtin_amdgcn_sinf(ub);
+}
+
+// The same normals times sigma, given g = -2 ln 2 sigma^2 (FP32): the
+// radius is sqrt(g log2 ua) = sigma sqrt(-2 ln ua).
+__device__ __forceinline__ void box_muller_r2(uint32_t wa, uint32_t wb, float g, float &z0, float &z1)
+{
+    const float ua = __builtin_fmaf((float)(wa >> 8), 0x1p-24f, 0x1p-24f);
+    const float ub = (float)(wb >> 8) * 0x1p-24f;
+    const float r = __builtin_amdgcn_sqrtf(g * __builtin_amdgcn_logf(ua));
     z0 = r * __builtin_amdgcn_cosf(ub);
     z1 = r * __builtin_amdgcn_sinf(ub);
 }

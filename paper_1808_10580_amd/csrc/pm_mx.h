@@ -29,7 +29,8 @@ struct MxHeader {
     float inv_scale;  // 2^-(coefficient shift + MX_BASIS_SHIFT)
     float cmax;       // max |Cx|, |Cy|
     float vbound;     // >= max over components of sum |C_c[i][j]| >= max |v| (torus; |phi| <= 1)
-    float pad[13];
+    float scale;      // 1 / inv_scale
+    float pad[12];
 };
 static_assert(sizeof(MxHeader) == 64, "operand alignment");
 
@@ -53,6 +54,9 @@ constexpr int MX_DISK_SHIFT = 30;
 struct MxTimeArgs {
     TimeArgs<float> t;           // chunk layout, steps, readouts, outputs (t.coef, t.sc unused)
     StepConsts<float> fx;        // dt (hi + lo) and sqrt(2 kappa dt), each x 2^32
+    // -2 ln 2 (2 kappa dt) 2^64: Box-Muller radius squared per log2 of the
+    // uniform, so that the normals come out times sqrt(2 kappa dt) 2^32
+    float gauss;
     const unsigned char *sets;   // [n_u][MX_SET_BYTES]
     // A parameter set whose vbound is at most vmax_fast moves a particle by
     // less than 0.45 of the period per step (drift plus the largest normal),

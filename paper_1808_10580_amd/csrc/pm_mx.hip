@@ -101,9 +101,10 @@ __global__ __launch_bounds__(256) void k_pack_mx(const MxPackArgs a, unsigned ch
     MxHeader *hd = reinterpret_cast<MxHeader *>(set);
     if (threadIdx.x == 0) {
         hd->inv_scale = ldexpf(1.f, -(sc + MX_BASIS_SHIFT));
+        hd->scale = ldexpf(1.f, sc + MX_BASIS_SHIFT);
         hd->cmax = (float)cmax;
         hd->vbound = (float)(vb * (1.0 + 0x1p-10));  // covers FP32 rounding of the bound and the bases
-        for (int q = 0; q < 13; ++q) hd->pad[q] = 0.f;
+        for (int q = 0; q < 12; ++q) hd->pad[q] = 0.f;
     }
     _Float16 *hi = reinterpret_cast<_Float16 *>(set + sizeof(MxHeader));
     _Float16 *lo = hi + 64 * 8;
@@ -262,10 +263,16 @@ __device__ __forceinline__ void mx_contract(const h16x8 ahi, const h16x8 alo, co
 // holds i, j <= 15 and the entry-16 row and column come from
 // `border` (MX_BORDER_FLOATS, wave-uniform) on the vector units:
 //   v_c += phi_16(x) sum_{j<=16} C_c[16][j] phi_j(y) + phi_16(y) sum_{i<16} C_c[i][16] phi_i(x).
+// The sums (sx, sy) are in the units of the packed coefficients, v = s x
+// inv_scale; `border` holds the border coefficients in the same units (times
+// the header's `scale`).  ix0, iy0 (column block 0) and ix1, iy1 (block 1)
+// start the y-form accumulators.  Each particle's sum adds one block-0
+// accumulator of one lane and one block-1 accumulator of another, so equal
+// values h in all four add 2h: a constant drift, halved, costs no instruction.
 template <int K>
-__device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, float inv, float xh, float yh,
-                                            float &vx, float &vy, MxPad &pad,
-                                            const float *__restrict__ border = nullptr)
+__device__ __forceinline__ void mx_velocity_sum(const h16x8 ahi, const h16x8 alo, float xh, float yh, float ix0,
+                                                float iy0, float ix1, float iy1, float &sx, float &sy, MxPad &pad,
+                                                const float *__restrict__ border = nullptr)
 {
     constexpr int B = 2 * K + 1;
     float px[17];
@@ -291,7 +298,7 @@ __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, fl
         Qy[q] = 2 * q + 1 < BT ? py[2 * q + 1] : 0.f;
         swap_halves(Py[q], Qy[q]);
     }
-    float ax0 = 0.f, ay0 = 0.f, ax1 = 0.f, ay1 = 0.f;
+    float ax0 = ix0, ay0 = iy0, ax1 = ix1, ay1 = iy1;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         ax0 = __builtin_fmaf(d0[q], Py[q], ax0);
@@ -304,8 +311,8 @@ __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, fl
     // lane adds (lower half-wave rows) + (upper half-wave rows).
     swap_halves(ax0, ax1);
     swap_halves(ay0, ay1);
-    vx = (ax0 + ax1) * inv;
-    vy = (ay0 + ay1) * inv;
+    sx = ax0 + ax1;
+    sy = ay0 + ay1;
     if constexpr (K == 8) {
         float r0 = 0.f, r1 = 0.f, s0 = 0.f, s1 = 0.f;
 #pragma unroll
@@ -319,9 +326,21 @@ __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, fl
             s1 = __builtin_fmaf(border[50 + i], px[i], s1);
         }
         const float p16 = px[16] * (1.0f / (float)(1 << MX_BASIS_SHIFT));  // phi_16(x), exact
-        vx = __builtin_fmaf(r0, p16, __builtin_fmaf(s0, py[16], vx));
-        vy = __builtin_fmaf(r1, p16, __builtin_fmaf(s1, py[16], vy));
+        sx = __builtin_fmaf(r0, p16, __builtin_fmaf(s0, py[16], sx));
+        sy = __builtin_fmaf(r1, p16, __builtin_fmaf(s1, py[16], sy));
     }
+}
+
+// The velocity itself (no drift): the sums scaled by inv_scale.
+template <int K>
+__device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, float inv, float xh, float yh,
+                                            float &vx, float &vy, MxPad &pad,
+                                            const float *__restrict__ border = nullptr)
+{
+    float sx, sy;
+    mx_velocity_sum<K>(ahi, alo, xh, yh, 0.f, 0.f, 0.f, 0.f, sx, sy, pad, border);
+    vx = sx * inv;
+    vy = sy * inv;
 }
 
 // Disk, psi = chi psi_F with chi = (1 - r^2)^2 (K <= 4, B <= 9): rows 8f + j
@@ -403,22 +422,21 @@ struct FixCoord {
     }
     __device__ __forceinline__ float at() const { return (float)(int32_t)X * 0x1p-32f; }
     __device__ __forceinline__ double value() const { return (double)(int32_t)X * 0x1p-32; }
-    __device__ __forceinline__ void advance(float vel, float z, const StepConsts<float> &c)
+    // Add an increment of d units, |d| < 2^31, truncated toward zero: where
+    // |d| >= 2^23 the FP32 value is a whole number already, below that the
+    // truncation moves the particle by less than 2^-32 of the period.
+    __device__ __forceinline__ void add(float d) { X += (uint32_t)(int32_t)d; }
+    // The increment of eq. (euler) in units: zs is the noise term
+    // sqrt(2 kappa dt) z already in units, dt in hi + lo parts.  Any size,
+    // reduced modulo the period first: with |d| held below 2^50 units, t = d
+    // 2^-32 and t + 1/2 are exact, q = floor(t + 1/2) is the nearest whole
+    // number of periods, and r = d - q 2^32 is exact (d and q 2^32 lie
+    // within a factor 2 of each other when q != 0) and in [-2^31, 2^31), an
+    // FP32 multiple of 128 units near its ends, so its rounding to a whole
+    // unit fits 32 bits.
+    __device__ __forceinline__ void advance_wide(float vel, float zs, const StepConsts<float> &c)
     {
-        float d = __builtin_fmaf(-c.dtl, vel, c.sq * z);
-        d = __builtin_fmaf(-c.dth, vel, d);
-        X += (uint32_t)(int32_t)__builtin_rintf(d);
-    }
-    // The same for an increment of any size, reduced modulo the period
-    // first: with |d| held below 2^50 units, t = d 2^-32 and t + 1/2 are
-    // exact, q = floor(t + 1/2) is the nearest whole number of periods, and
-    // r = d - q 2^32 is exact (d and q 2^32 lie within a factor 2 of each
-    // other when q != 0) and in [-2^31, 2^31), an FP32 multiple of 128 units
-    // near its ends, so its rounding to a whole unit fits 32 bits.  Equal to
-    // advance whenever |d| < 2^31 - 64.
-    __device__ __forceinline__ void advance_wide(float vel, float z, const StepConsts<float> &c)
-    {
-        float d = __builtin_fmaf(-c.dtl, vel, c.sq * z);
+        float d = __builtin_fmaf(-c.dtl, vel, zs);
         d = __builtin_fmaf(-c.dth, vel, d);
         d = __builtin_fminf(__builtin_fmaxf(d, -0x1p50f), 0x1p50f);
         const float q = __builtin_floorf(__builtin_fmaf(d, 0x1p-32f, 0.5f));
@@ -481,10 +499,13 @@ __device__ __forceinline__ float set_vbound(const unsigned char *__restrict__ se
 // Algorithm 1, persistent: one task is one 64-particle chunk of one parameter
 // set, one wave per task; lane l of chunk q of observation j runs particle
 // i = 64 q + l (the chunk layout and the Philox streams of the vector time
-// kernel, so the payoff and reduction kernels are shared).
+// kernel, so the payoff and reduction kernels are shared).  Register
+// budget: 96 per lane (5 waves per SIMD); the single-readout K = 6 kernel
+// fits 80 without spills (6 waves per SIMD).
 // ---------------------------------------------------------------------------
 template <int K, bool MT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_time_mx(const MxTimeArgs m)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 6 && !MT ? 6 : 5))) void k_time_mx(
+    const MxTimeArgs m)
 {
     // K = 8: the border coefficients of the wave's parameter set, re-read from
     // LDS at every step (broadcast) rather than held in 66 registers
@@ -495,7 +516,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     float *my_border = s_border + (K == 8 ? (threadIdx.x >> 6) * NBD : 0);
     int cur_b = -1;
     h16x8 ahi = {}, alo = {};
-    float inv = 0.f;
+    float inv = 0.f, gh = 0.f, hx = 0.f, hy = 0.f;
     bool wide = false;
     MxPad pad;
     for (;;) {
@@ -526,11 +547,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         if (b != cur_b) {
             const unsigned char *set = m.sets + (int64_t)b * MX_SET_BYTES;
             load_set(set, lane, ahi, alo, inv);
-            wide = !(set_vbound(set) <= m.vmax_fast);  // wave-uniform; NaN takes the wide path
+            const float scale = reinterpret_cast<const MxHeader *>(set)->scale;
+            // the constant drift in the units of the sums, half of it in each
+            // of the two accumulators that end in a particle's sum (wave-uniform)
+            const float v0xs = a.v0x * scale, v0ys = a.v0y * scale;
+            hx = 0.5f * v0xs;
+            hy = 0.5f * v0ys;
+            gh = -m.fx.dth * inv;  // exact: inv is a power of two
+            // wave-uniform; NaN takes the wide path
+            wide = !(set_vbound(set) <= m.vmax_fast && fmaxf(fabsf(v0xs), fabsf(v0ys)) <= 0x1p100f);
             if constexpr (K == 8) {
                 const float *src = reinterpret_cast<const float *>(set + MX_BORDER_OFFSET);
                 wave_lds_sync();
-                for (int e = lane; e < NBD; e += 64) my_border[e] = src[e];
+                for (int e = lane; e < NBD; e += 64) my_border[e] = src[e] * scale;
                 wave_lds_sync();
             }
             cur_b = b;
@@ -567,27 +596,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         };
         readout(0);
         // the step loop, with the 32-bit or (set with a large velocity bound)
-        // the 64-bit increment
+        // the 64-bit increment.  The normals come scaled by sqrt(2 kappa dt)
+        // in units (m.gauss); the 32-bit step forms the increment as
+        // -dt v + noise in one FMA on the unscaled sums, dt rounded once to
+        // FP32 in units x inv_scale (relative error 2^-24 of the drift).
         auto walk = [&](auto wide_c) {
             constexpr bool WIDE = decltype(wide_c)::value;
             auto step = [&](float z0, float z1) {
-                float vx, vy;
+                float sx, sy;
                 if constexpr (K == 8) __asm__ volatile("" ::: "memory");  // re-read the borders every step
-                mx_velocity<K>(ahi, alo, inv, x.at(), y.at(), vx, vy, pad, my_border);
                 if constexpr (WIDE) {
-                    x.advance_wide(vx + a.v0x, z0, m.fx);
-                    y.advance_wide(vy + a.v0y, z1, m.fx);
+                    mx_velocity_sum<K>(ahi, alo, x.at(), y.at(), 0.f, 0.f, 0.f, 0.f, sx, sy, pad, my_border);
+                    x.advance_wide(__builtin_fmaf(sx, inv, a.v0x), z0, m.fx);
+                    y.advance_wide(__builtin_fmaf(sy, inv, a.v0y), z1, m.fx);
                 } else {
-                    x.advance(vx + a.v0x, z0, m.fx);
-                    y.advance(vy + a.v0y, z1, m.fx);
+                    mx_velocity_sum<K>(ahi, alo, x.at(), y.at(), hx, hy, hx, hy, sx, sy, pad, my_border);
+                    x.add(__builtin_fmaf(gh, sx, z0));
+                    y.add(__builtin_fmaf(gh, sy, z1));
                 }
             };
             int64_t n = 0;
             for (; n + 1 < a.n_steps; n += 2) {
                 const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi, pj, k0, k1);
                 float z0, z1, z2, z3;
-                box_muller(w.x, w.y, z0, z1);
-                box_muller(w.z, w.w, z2, z3);
+                box_muller_r2(w.x, w.y, m.gauss, z0, z1);
+                box_muller_r2(w.z, w.w, m.gauss, z2, z3);
                 step(z0, z1);
                 readout(n + 1);
                 step(z2, z3);
@@ -596,7 +629,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             if (n < a.n_steps) {
                 const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi, pj, k0, k1);
                 float z0, z1;
-                box_muller(w.x, w.y, z0, z1);
+                box_muller_r2(w.x, w.y, m.gauss, z0, z1);
                 step(z0, z1);
                 readout(n + 1);
             }
@@ -623,9 +656,10 @@ __global__ __launch_bounds__(256) void k_step_mx(const MxStepArgs a)
     h16x8 ahi, alo;
     float inv;
     load_set(a.set, lane, ahi, alo, inv);
-    if constexpr (K == 8) {
+    if constexpr (K == 8) {  // border coefficients in the units of the packed ones
         if (threadIdx.x < MX_BORDER_FLOATS + 2)
-            s_border[threadIdx.x] = reinterpret_cast<const float *>(a.set + MX_BORDER_OFFSET)[threadIdx.x];
+            s_border[threadIdx.x] = reinterpret_cast<const float *>(a.set + MX_BORDER_OFFSET)[threadIdx.x] *
+                                    reinterpret_cast<const MxHeader *>(a.set)->scale;
         __syncthreads();
     }
     FixCoord x, y;
@@ -645,8 +679,8 @@ __global__ __launch_bounds__(256) void k_step_mx(const MxStepArgs a)
     float z0, z1;
     if ((n & 1) == 0) box_muller(w.x, w.y, z0, z1);
     else box_muller(w.z, w.w, z0, z1);
-    x.advance_wide(vx + a.v0x, z0, a.fx);
-    y.advance_wide(vy + a.v0y, z1, a.fx);
+    x.advance_wide(vx + a.v0x, a.fx.sq * z0, a.fx);
+    y.advance_wide(vy + a.v0y, a.fx.sq * z1, a.fx);
     double nx = x.value(), ny = y.value();
     nx -= floor(nx);
     ny -= floor(ny);
