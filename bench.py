@@ -44,8 +44,8 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 COUNTER_TRAFFIC = {
     # k_time<float,6,3>: FETCH 157.25 KiB x 2 + WRITE 77,480.78 KiB x 1
     "valu": (79_662_368, "3b284018099e00ed8b8ca29fbfcbd81e7f33371ba6f8cff6f3ffc09d0a75e464"),
-    # k_time_mx<6>: FETCH 64.38 KiB x 2 + WRITE 79,172.34 KiB x 1
-    "mfma": (81_204_066, "5a9dae26a3cc17174fd8d5ddad13a8886aaaac3f1cdc9a390b4cd80e408030e1"),
+    # k_time_mx<6>: FETCH 62.19 KiB x 2 + WRITE 79,140.34 KiB x 1
+    "mfma": (81_166_818, "4560017ae817a31034137823e406a326421112bc992b80ba16825dfa1df1f047"),
 }
 # The same for the dominant kernel of the other workloads (bench.py
 # --workload ...), keyed by (workload, velocity engine): (bytes per launch,
@@ -81,10 +81,10 @@ PEAK_FP16_DENSE_TFLOPS = 2500.0
 # slots (slots x 4 cycles per wave64 slot / 64 lanes per wave, over the
 # kernel's cycles per SIMD).
 COUNTERS = {
-    "mfma": ({"valu_insts": 142.1, "valu_slots": 181.1, "fma_f32": 49.0, "mul_f32": 8.0, "add_f32": 4.0,
-              "issue_frac": 1.00, "mfma_busy": 0.265,
+    "mfma": ({"valu_insts": 130.1, "valu_slots": 164.1, "fma_f32": 47.0, "mul_f32": 6.0, "add_f32": 4.0,
+              "issue_frac": 1.03, "mfma_busy": 0.301,
               "source": "profiles/k_time_mx_torus-k6-fp32_pmc.md"},
-             "5a9dae26a3cc17174fd8d5ddad13a8886aaaac3f1cdc9a390b4cd80e408030e1"),
+             "4560017ae817a31034137823e406a326421112bc992b80ba16825dfa1df1f047"),
     "valu": (None, ""),
 }
 

@@ -115,15 +115,17 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float &z0, 
     z1 = r * __builtin_amdgcn_sinf(ub);
 }
 
-// The same normals times sigma, given g = -2 ln 2 sigma^2 (FP32): the
-// radius is sqrt(g log2 ua) = sigma sqrt(-2 ln ua).
-__device__ __forceinline__ void box_muller_r2(uint32_t wa, uint32_t wb, float g, float &z0, float &z1)
+// The same normals times sigma plus offsets, given g = -2 ln 2 sigma^2 (FP32):
+// the radius is sqrt(g log2 ua) = sigma sqrt(-2 ln ua), and each product
+// with cos / sin takes its offset in the same FMA.
+__device__ __forceinline__ void box_muller_r2(uint32_t wa, uint32_t wb, float g, float c0, float c1, float &z0,
+                                              float &z1)
 {
     const float ua = __builtin_fmaf((float)(wa >> 8), 0x1p-24f, 0x1p-24f);
     const float ub = (float)(wb >> 8) * 0x1p-24f;
     const float r = __builtin_amdgcn_sqrtf(g * __builtin_amdgcn_logf(ua));
-    z0 = r * __builtin_amdgcn_cosf(ub);
-    z1 = r * __builtin_amdgcn_sinf(ub);
+    z0 = __builtin_fmaf(r, __builtin_amdgcn_cosf(ub), c0);
+    z1 = __builtin_fmaf(r, __builtin_amdgcn_sinf(ub), c1);
 }
 
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double &z0, double &z1)

@@ -25,6 +25,75 @@ constexpr int64_t MX_BORDER_OFFSET = 2112;
 constexpr int64_t MX_SET_BYTES = MX_BORDER_OFFSET + 4 * (MX_BORDER_FLOATS + 2);
 static_assert(MX_SET_BYTES % 16 == 0, "set alignment");
 
+// Tile layout of the small-K torus and disk paths.  Basis entry 0 is the
+// constant S (x basis) or 1 (y basis); entries 2v + 1, 2v + 2 (v = 0..K-1)
+// are cos and sin of harmonic v + 1.
+//
+// x basis, the 16-entry contraction dimension: slot s = 8 h + 2 d + t sits in
+// operand register d (half t) of half-wave h.  For K <= 7 register 0 of the
+// lower half holds (entry 0, padding), that of the upper half padding (K <= 6)
+// or the pair v = 6 (K = 7), and the pairs v = 0..5 fill registers 1..3,
+// lower half first: (h, d) = (v mod 2, 1 + v / 2).  Then the constant needs
+// no FP16 split and, with no varying pair beside it, no half-wave swap.  At
+// K = 8 (16 entries in the tile) slot s holds entry s.  Returns -1 for
+// padding.
+__host__ __device__ constexpr int mx_x_entry(int K, int s)
+{
+    if (K >= 8) return s;
+    const int h = s >> 3, d = (s & 7) >> 1, t = s & 1;
+    if (d == 0) {
+        if (h == 0) return t == 0 ? 0 : -1;
+        return K == 7 ? 2 * 6 + 1 + t : -1;
+    }
+    const int v = 2 * (d - 1) + h;
+    return v < K ? 2 * v + 1 + t : -1;
+}
+
+// y basis, torus: accumulator register q of half-wave h (tile row
+// 8 (q / 4) + 4 h + q mod 4 of each form) meets entry 2q + 2 (h = 0) and 2q + 1
+// (h = 1) for q < min(K, 7), so that one half-wave swap of the pair
+// (2q + 2, 2q + 1) serves both column blocks; register min(K, 7) holds entry
+// 0 (h = 0; constant 1, no swap) and padding (h = 1; entry 15 at K = 8).
+// Returns -1 for padding.
+__host__ __device__ constexpr int mx_y_entry(int K, int q, int h)
+{
+    const int m = K < 7 ? K : 7;
+    if (q < m) return h == 0 ? 2 * q + 2 : 2 * q + 1;
+    if (q == m) return h == 0 ? 0 : (K == 8 ? 15 : -1);
+    return -1;
+}
+
+// Every basis entry the tile holds (min(2K + 1, 16) per axis) in exactly one
+// slot / row, and each x register pair of one of the kinds mx_contract handles.
+__host__ __device__ constexpr bool mx_layout_ok(int K)
+{
+    const int n = 2 * K + 1 < 16 ? 2 * K + 1 : 16;
+    for (int e = 0; e < n; ++e) {
+        int cx = 0, cy = 0;
+        for (int s = 0; s < 16; ++s) cx += mx_x_entry(K, s) == e;
+        for (int q = 0; q < 8; ++q)
+            for (int h = 0; h < 2; ++h) cy += mx_y_entry(K, q, h) == e;
+        if (cx != 1 || cy != 1) return false;
+    }
+    for (int s = 0; s < 16; ++s)
+        if (mx_x_entry(K, s) >= n) return false;
+    for (int d = 0; d < 4; ++d) {
+        for (int h = 0; h < 2; ++h) {
+            const int e0 = mx_x_entry(K, 8 * h + 2 * d), e1 = mx_x_entry(K, 8 * h + 2 * d + 1);
+            if (e0 < 0 && e1 >= 0) return false;  // padding before an entry
+        }
+        const bool p_var = mx_x_entry(K, 2 * d) > 0 || mx_x_entry(K, 2 * d + 1) >= 0;
+        const bool q_var = mx_x_entry(K, 8 + 2 * d) > 0 || mx_x_entry(K, 8 + 2 * d + 1) >= 0;
+        const bool q_pad = mx_x_entry(K, 8 + 2 * d) < 0;
+        if (!p_var && q_var && mx_x_entry(K, 2 * d) != 0) return false;  // padding P, varying Q
+        if (p_var && !q_var && !q_pad) return false;                      // varying P, constant Q
+    }
+    return true;
+}
+static_assert(mx_layout_ok(1) && mx_layout_ok(2) && mx_layout_ok(3) && mx_layout_ok(4) && mx_layout_ok(5) &&
+                  mx_layout_ok(6) && mx_layout_ok(7) && mx_layout_ok(8),
+              "small-K tile layout");
+
 struct MxHeader {
     float inv_scale;  // 2^-(coefficient shift + MX_BASIS_SHIFT)
     float cmax;       // max |Cx|, |Cy|

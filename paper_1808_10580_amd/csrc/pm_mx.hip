@@ -110,18 +110,18 @@ __global__ __launch_bounds__(256) void k_pack_mx(const MxPackArgs a, unsigned ch
     _Float16 *lo = hi + 64 * 8;
     for (int t = threadIdx.x; t < 64 * 8; t += blockDim.x) {
         const int lane = t >> 3, e = t & 7;
-        const int row = lane & 31, i = 8 * (lane >> 5) + e;
+        const int row = lane & 31, i = mx_x_entry(a.K, 8 * (lane >> 5) + e);
         int comp, j;
-        if (nf == 2) {  // torus: rows 0..15 Cx, 16..31 Cy; row 8(q/4) + 4h + q%4 holds j = 2q + h
+        if (nf == 2) {  // torus: rows 0..15 Cx, 16..31 Cy; row 8(q/4) + 4h + q%4 is register q, half h
             comp = row >> 4;
             const int r = row & 15;
-            j = 2 * (4 * (r >> 3) + (r & 3)) + ((r >> 2) & 1);
+            j = mx_y_entry(a.K, 4 * (r >> 3) + (r & 3), (r >> 2) & 1);
         } else {  // disk: rows 8f + j (j < 8) and 24 + f (j = 8) for form f
             comp = row < 24 ? row >> 3 : (row < 27 ? row - 24 : -1);
             j = row < 24 ? row & 7 : 8;
         }
         double v = 0.0;
-        if (comp >= 0 && i < B && j < B) v = ldexp(C[j * R + nf * i + comp], sc);
+        if (comp >= 0 && i >= 0 && i < B && j >= 0 && j < B) v = ldexp(C[j * R + nf * i + comp], sc);
         const _Float16 h = (_Float16)(float)v;
         hi[t] = h;
         lo[t] = (_Float16)(float)(v - (double)(float)h);
@@ -196,47 +196,76 @@ __device__ __forceinline__ void cheb_basis(float s, float S, float *phi)
 // partner's entries 2d, 2d + 1 needs no fresh zero register each time.
 struct MxPad {
     uint32_t h[4] = {0u, 0u, 0u, 0u}, l[4] = {0u, 0u, 0u, 0u};
+    // the constant register of both column blocks (hi: entry 0 in FP16, lo: zero)
+    uint32_t ch[2] = {(uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(float)(1 << MX_BASIS_SHIFT)),
+                      (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(float)(1 << MX_BASIS_SHIFT))};
+    uint32_t cl[2] = {0u, 0u};
 };
 
 // The contraction W = A^T Phi_x for the 64 particles of a wave: x basis
-// (px, from cheb_basis) split into FP16 pairs (P holds entries 0..7, Q
-// 8..15; entries past B are padding), the half-wave swaps that make P the B operand of
-// column block 0 (particles 0..31) and Q that of block 1 (32..63), and the three split
-// products per block.  A register pair whose entries are all padding in both
-// P and Q is not swapped (zero); one whose Q entries alone are padding swaps
-// P with the carried padding register of `pad` (a swap writes the upper
-// half-wave of P and the lower half-wave of its partner, so the carried
-// register's upper half keeps its initial zero and its lower half receives
-// the partner's P entries, while P's upper half takes finite values of the
-// previous call into padding rows).
+// (px, from cheb_basis) split into FP16 pairs in the slots of mx_x_entry (P:
+// the lower half-wave's registers, Q: the upper's), the half-wave swaps that
+// make P the B operand of column block 0 (particles 0..31) and Q that of
+// block 1 (32..63), and the three split products per block.  Per register:
+// both halves constant or padding: a constant register, the same in every
+// lane and block (padding slots meet zero coefficients, so any finite value
+// serves there), no swap; both varying: one swap each for hi and lo; P
+// varying and Q padding: P is swapped with the carried padding register of
+// `pad` (a swap writes the upper half-wave of P and the lower half-wave of
+// its partner, so the carried register's upper half keeps its initial zero
+// and its lower half receives the partner's P entries, while P's upper half
+// takes finite values of the previous call into padding slots); P constant
+// and Q varying (K = 7): the constant is set again before each swap.
 template <int K>
 __device__ __forceinline__ void mx_contract(const h16x8 ahi, const h16x8 alo, const float *px, f32x16 &d0,
                                             f32x16 &d1, MxPad &pad)
 {
-    constexpr int B = 2 * K + 1 < 16 ? 2 * K + 1 : 16;  // entries in the tile
     static_assert(K >= 1 && K <= MX_MAX_K, "small-K path");
+    // register kinds: 0 padding, 1 the constant entry 0 (with padding), 2 varying
+    constexpr auto kind = [](int h, int d) {
+        const int e0 = mx_x_entry(K, 8 * h + 2 * d), e1 = mx_x_entry(K, 8 * h + 2 * d + 1);
+        if (e0 < 0 && e1 < 0) return 0;
+        if (e0 == 0 && e1 < 0) return 1;
+        return 2;
+    };
+    // entry 0 in FP16: S in the low half, the padding slot beside it zero
+    const uint32_t chi = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(float)(1 << MX_BASIS_SHIFT));
     uint32_t Ph[4], Pl[4], Qh[4], Ql[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
-            const int e = 8 * half + 2 * d;
+            const int e0 = mx_x_entry(K, 8 * half + 2 * d), e1 = mx_x_entry(K, 8 * half + 2 * d + 1);
             uint32_t hi = 0u, lo = 0u;
-            if (e < B) split_pair(px[e], e + 1 < B ? px[e + 1] : 0.f, hi, lo);
+            if (kind(half, d) == 2) split_pair(px[e0 < 0 ? 0 : e0], e1 < 0 ? 0.f : px[e1], hi, lo);
+            else if (kind(half, d) == 1) hi = chi;
             (half ? Qh : Ph)[d] = hi;
             (half ? Ql : Pl)[d] = lo;
         }
     }
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-        if (2 * d >= B) continue;  // all padding: zero in both halves, nothing to move
-        if (8 + 2 * d >= B) {      // Q padding: swap with the carried register
+        const int kp = kind(0, d), kq = kind(1, d);
+        if (kp != 2 && kq != 2) {  // constant or padding in both halves
+            if (kp == 1 || kq == 1) {
+                __asm__ volatile("" : "+v"(pad.ch[0]), "+v"(pad.ch[1]), "+v"(pad.cl[0]), "+v"(pad.cl[1]));
+                Ph[d] = pad.ch[0];
+                Qh[d] = pad.ch[1];
+                Pl[d] = pad.cl[0];
+                Ql[d] = pad.cl[1];
+            } else {
+                Qh[d] = Ph[d] = 0u;
+                Ql[d] = Pl[d] = 0u;
+            }
+            continue;
+        }
+        if (kq == 0) {  // Q padding: swap with the carried register
             Qh[d] = pad.h[d];
             Ql[d] = pad.l[d];
         }
         swap_halves(Ph[d], Qh[d]);
         swap_halves(Pl[d], Ql[d]);
-        if (8 + 2 * d >= B) {
+        if (kq == 0) {
             pad.h[d] = Qh[d];
             pad.l[d] = Ql[d];
         }
@@ -256,23 +285,22 @@ __device__ __forceinline__ void mx_contract(const h16x8 ahi, const h16x8 alo, co
 }
 
 // Torus: rows r < 16 hold Cx[.][j], rows r >= 16 Cy[.][j], with tile row
-// r mod 16 = 8 (q / 4) + 4 h + q mod 4 holding j = 2 q + h (k_pack_mx): D
-// register q of a lower-half lane then meets y entry 2q and the same
-// register of an upper-half lane entry 2q + 1, so the registers q with
-// 2q >= B hold zero rows in both halves and drop out.  At K = 8 the tile
+// r mod 16 = 8 (q / 4) + 4 h + q mod 4 holding j = mx_y_entry(K, q, h)
+// (k_pack_mx): D register q of a lower-half lane meets y entry 2q + 2 and the
+// same register of an upper-half lane entry 2q + 1, so one swap of that pair
+// serves both column blocks; register min(K, 7) meets the constant entry 0
+// (and padding, or entry 15 at K = 8) and the registers past it hold zero
+// rows in both halves and drop out.  At K = 8 the tile
 // holds i, j <= 15 and the entry-16 row and column come from
 // `border` (MX_BORDER_FLOATS, wave-uniform) on the vector units:
 //   v_c += phi_16(x) sum_{j<=16} C_c[16][j] phi_j(y) + phi_16(y) sum_{i<16} C_c[i][16] phi_i(x).
 // The sums (sx, sy) are in the units of the packed coefficients, v = s x
 // inv_scale; `border` holds the border coefficients in the same units (times
-// the header's `scale`).  ix0, iy0 (column block 0) and ix1, iy1 (block 1)
-// start the y-form accumulators.  Each particle's sum adds one block-0
-// accumulator of one lane and one block-1 accumulator of another, so equal
-// values h in all four add 2h: a constant drift, halved, costs no instruction.
+// the header's `scale`).  At K <= 7 the rows of entry 0 (times the constant
+// 1) start the y-form accumulators.
 template <int K>
-__device__ __forceinline__ void mx_velocity_sum(const h16x8 ahi, const h16x8 alo, float xh, float yh, float ix0,
-                                                float iy0, float ix1, float iy1, float &sx, float &sy, MxPad &pad,
-                                                const float *__restrict__ border = nullptr)
+__device__ __forceinline__ void mx_velocity_sum(const h16x8 ahi, const h16x8 alo, float xh, float yh, float &sx,
+                                                float &sy, MxPad &pad, const float *__restrict__ border = nullptr)
 {
     constexpr int B = 2 * K + 1;
     float px[17];
@@ -282,23 +310,35 @@ __device__ __forceinline__ void mx_velocity_sum(const h16x8 ahi, const h16x8 alo
     f32x16 d0, d1;
     mx_contract<K>(ahi, alo, px, d0, d1, pad);
 
-    // y basis (FP32, unscaled) while the matrix cores work: Py = entries 2q,
-    // Qy = entries 2q + 1; after the swaps Py serves column block 0 and Qy
-    // block 1, matching D register q (x rows) and 8 + q (y rows)
-    constexpr int BT = B < 16 ? B : 16;  // y entries in the tile
-    constexpr int NQ = (BT + 1) / 2;      // D registers with a nonzero row
+    // y basis (FP32, unscaled) while the matrix cores work: Py = entries
+    // 2q + 2, Qy = entries 2q + 1; after the swaps Py serves column block 0
+    // and Qy block 1, matching D register q (x rows) and 8 + q (y rows).
+    // Register M = min(K, 7) meets entry 0 (= 1) in the lower half-wave and
+    // zero rows in the upper one at K <= 7, so it starts the sums; at K = 8
+    // its upper half meets entry 15, carried over by one more swap.
+    constexpr int M = K < 7 ? K : 7;
+    constexpr int NQ = K == 8 ? M + 1 : M;  // registers multiplied by a y entry
     float py[17];
     cheb_basis<K>(yh, 1.f, py);
 #pragma unroll
     for (int e = B; e < 17; ++e) py[e] = 0.f;
-    float Py[NQ], Qy[NQ];
+    float Py[M + 1], Qy[M + 1];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        Py[q] = py[2 * q];
-        Qy[q] = 2 * q + 1 < BT ? py[2 * q + 1] : 0.f;
+    for (int q = 0; q < M; ++q) {
+        Py[q] = py[2 * q + 2];
+        Qy[q] = py[2 * q + 1];
         swap_halves(Py[q], Qy[q]);
     }
-    float ax0 = ix0, ay0 = iy0, ax1 = ix1, ay1 = iy1;
+    Py[M] = 1.f;
+    Qy[M] = K == 8 ? py[15] : 1.f;
+    if constexpr (K == 8) swap_halves(Py[M], Qy[M]);
+    float ax0 = 0.f, ay0 = 0.f, ax1 = 0.f, ay1 = 0.f;
+    if constexpr (K < 8) {
+        ax0 = d0[M];
+        ay0 = d0[8 + M];
+        ax1 = d1[M];
+        ay1 = d1[8 + M];
+    }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         ax0 = __builtin_fmaf(d0[q], Py[q], ax0);
@@ -338,7 +378,7 @@ __device__ __forceinline__ void mx_velocity(const h16x8 ahi, const h16x8 alo, fl
                                             const float *__restrict__ border = nullptr)
 {
     float sx, sy;
-    mx_velocity_sum<K>(ahi, alo, xh, yh, 0.f, 0.f, 0.f, 0.f, sx, sy, pad, border);
+    mx_velocity_sum<K>(ahi, alo, xh, yh, sx, sy, pad, border);
     vx = sx * inv;
     vy = sy * inv;
 }
@@ -500,11 +540,12 @@ __device__ __forceinline__ float set_vbound(const unsigned char *__restrict__ se
 // set, one wave per task; lane l of chunk q of observation j runs particle
 // i = 64 q + l (the chunk layout and the Philox streams of the vector time
 // kernel, so the payoff and reduction kernels are shared).  Register
-// budget: 96 per lane (5 waves per SIMD); the single-readout K = 6 kernel
-// fits 80 without spills (6 waves per SIMD).
+// budget: 96 per lane (5 waves per SIMD; K = 6 uses 91 without spills, and a
+// budget of 80 for 6 waves per SIMD spilled around the step loop for the same
+// time per map).
 // ---------------------------------------------------------------------------
 template <int K, bool MT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 6 && !MT ? 6 : 5))) void k_time_mx(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_time_mx(
     const MxTimeArgs m)
 {
     // K = 8: the border coefficients of the wave's parameter set, re-read from
@@ -516,7 +557,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 6 && !
     float *my_border = s_border + (K == 8 ? (threadIdx.x >> 6) * NBD : 0);
     int cur_b = -1;
     h16x8 ahi = {}, alo = {};
-    float inv = 0.f, gh = 0.f, hx = 0.f, hy = 0.f;
+    float inv = 0.f, gh = 0.f, cx = 0.f, cy = 0.f;
     bool wide = false;
     MxPad pad;
     for (;;) {
@@ -547,18 +588,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 6 && !
         if (b != cur_b) {
             const unsigned char *set = m.sets + (int64_t)b * MX_SET_BYTES;
             load_set(set, lane, ahi, alo, inv);
-            const float scale = reinterpret_cast<const MxHeader *>(set)->scale;
-            // the constant drift in the units of the sums, half of it in each
-            // of the two accumulators that end in a particle's sum (wave-uniform)
-            const float v0xs = a.v0x * scale, v0ys = a.v0y * scale;
-            hx = 0.5f * v0xs;
-            hy = 0.5f * v0ys;
             gh = -m.fx.dth * inv;  // exact: inv is a power of two
-            // wave-uniform; NaN takes the wide path
-            wide = !(set_vbound(set) <= m.vmax_fast && fmaxf(fabsf(v0xs), fabsf(v0ys)) <= 0x1p100f);
+            cx = -m.fx.dth * a.v0x;  // the constant drift's increment in units
+            cy = -m.fx.dth * a.v0y;
+            wide = !(set_vbound(set) <= m.vmax_fast);  // wave-uniform; NaN takes the wide path
             if constexpr (K == 8) {
                 const float *src = reinterpret_cast<const float *>(set + MX_BORDER_OFFSET);
                 wave_lds_sync();
+                const float scale = reinterpret_cast<const MxHeader *>(set)->scale;
                 for (int e = lane; e < NBD; e += 64) my_border[e] = src[e] * scale;
                 wave_lds_sync();
             }
@@ -597,30 +634,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 6 && !
         readout(0);
         // the step loop, with the 32-bit or (set with a large velocity bound)
         // the 64-bit increment.  The normals come scaled by sqrt(2 kappa dt)
-        // in units (m.gauss); the 32-bit step forms the increment as
-        // -dt v + noise in one FMA on the unscaled sums, dt rounded once to
+        // in units (m.gauss); the 32-bit step takes the constant drift's
+        // increment -dt v0 in the same FMAs (cx, cy) and forms the increment
+        // as -dt v + noise in one FMA on the unscaled sums, dt rounded once to
         // FP32 in units x inv_scale (relative error 2^-24 of the drift).
         auto walk = [&](auto wide_c) {
             constexpr bool WIDE = decltype(wide_c)::value;
             auto step = [&](float z0, float z1) {
                 float sx, sy;
                 if constexpr (K == 8) __asm__ volatile("" ::: "memory");  // re-read the borders every step
+                mx_velocity_sum<K>(ahi, alo, x.at(), y.at(), sx, sy, pad, my_border);
                 if constexpr (WIDE) {
-                    mx_velocity_sum<K>(ahi, alo, x.at(), y.at(), 0.f, 0.f, 0.f, 0.f, sx, sy, pad, my_border);
                     x.advance_wide(__builtin_fmaf(sx, inv, a.v0x), z0, m.fx);
                     y.advance_wide(__builtin_fmaf(sy, inv, a.v0y), z1, m.fx);
                 } else {
-                    mx_velocity_sum<K>(ahi, alo, x.at(), y.at(), hx, hy, hx, hy, sx, sy, pad, my_border);
                     x.add(__builtin_fmaf(gh, sx, z0));
                     y.add(__builtin_fmaf(gh, sy, z1));
                 }
             };
+            const float ox = WIDE ? 0.f : cx, oy = WIDE ? 0.f : cy;
             int64_t n = 0;
             for (; n + 1 < a.n_steps; n += 2) {
                 const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi, pj, k0, k1);
                 float z0, z1, z2, z3;
-                box_muller_r2(w.x, w.y, m.gauss, z0, z1);
-                box_muller_r2(w.z, w.w, m.gauss, z2, z3);
+                box_muller_r2(w.x, w.y, m.gauss, ox, oy, z0, z1);
+                box_muller_r2(w.z, w.w, m.gauss, ox, oy, z2, z3);
                 step(z0, z1);
                 readout(n + 1);
                 step(z2, z3);
@@ -629,7 +667,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 6 && !
             if (n < a.n_steps) {
                 const U4 w = philox4x32_10_wu((uint32_t)(n >> 1), pi, pj, k0, k1);
                 float z0, z1;
-                box_muller_r2(w.x, w.y, m.gauss, z0, z1);
+                box_muller_r2(w.x, w.y, m.gauss, ox, oy, z0, z1);
                 step(z0, z1);
                 readout(n + 1);
             }
