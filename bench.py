@@ -330,6 +330,8 @@ def bench_other(args):
     dev = torch.device("cuda", 0)
     ctx = pm.Context(0)
     ctx.set_velocity_engine(args.engine)
+    if args.dir_tail >= 0:
+        ctx.set_dirichlet_tail(args.dir_tail)
     name = args.workload
     cpu = None
     calibration_copy(torch, dev, args.copy_mib)
@@ -388,8 +390,10 @@ def bench_other(args):
         fl = alg_flops_per_particle_step(len(wl.modes), K, "disk")
         eng = engine_in_use(pm, args.engine, K, "disk")
         mx = eng == "mfma"
+        tail_on = mx and args.dir_tail != 0  # the library's default hands sparse waves to the tail
+        kname = f"k_dirichlet_mx<{K}>" + (f" + k_dirichlet_tail<{K}>" if tail_on else "")
         rl = {"bound": "mfma" if mx else "alu", "peak": PEAK_FP16_DENSE_TFLOPS if mx else PEAK_FP32_TFLOPS,
-              "unit": "TFLOP/s", "kernel": f"k_dirichlet_mx<{K}>" if mx else f"k_dirichlet<float,{K}>",
+              "unit": "TFLOP/s", "kernel": kname if mx else f"k_dirichlet<float,{K}>",
               "flop_per_particle_step": fl,
               "flop_count": "mode sum of eq. v_expand with the disk cutoff: 18 per mode + 12 per harmonic + 36",
               "peak_of": "dense FP16 matrix" if mx else "FP32 vector",
@@ -546,6 +550,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the (untimed) kernel-variant autotuning before the timed steps")
     ap.add_argument("--model", default=None, help="pcn workload: a surrogate model file (da_prior train)")
+    ap.add_argument("--dir-tail", type=int, default=-1,
+                    help="disk walk: live lanes below which waves hand their walkers to the cooperative tail "
+                         "(0 = off, -1 = library default)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 512-set batched map reported beside the main line")
     ap.add_argument("--copy-mib", type=int, default=0,

@@ -379,6 +379,26 @@ int pm_set_dirichlet_blocks_per_cu(pm_ctx *ctx, int blocks_per_cu);
  * whose tails are wide rather than long. */
 int pm_set_dirichlet_compaction(pm_ctx *ctx, int dump_below, int launches);
 
+/* Cooperative tail of the matrix-core disk walk (Algorithm 2 on the unit
+ * disk, FP32, K <= 4, zero, constant or linear source; other paths ignore
+ * it; default live_below 4).  Once no fresh particle is left, a wave whose live lanes drop below
+ * live_below (after 1,024 iterations in its launch) saves its walkers to a
+ * pool and ends; one more launch runs every saved walker to its exit, one
+ * walker per wave: the 64 lanes share each step (lane 16 f + j forms column
+ * j of velocity form f, a row-wise sum adds them; one Philox draw per lane
+ * gives the normals of 128 steps), so a long walk advances several times
+ * faster than alone in a wave of the matrix-core walk.  Same walk, random
+ * numbers, exit rule and cap; the velocity is summed in another order than
+ * the matrix-core contraction, so a continued path differs from an
+ * uninterrupted one in rounding, within the same FP32 bounds.  live_below in
+ * 0..64 (0: off); while on, the compaction setting does not apply to this
+ * path.  PM_EINVAL outside that range. */
+int pm_set_dirichlet_tail(pm_ctx *ctx, int live_below);
+
+/* Walkers the last Dirichlet call on ctx handed to the cooperative tail
+ * (0 when the tail did not run).  Synchronises the context's stream. */
+int pm_dirichlet_tail_walkers(pm_ctx *ctx, int64_t *walkers);
+
 /* Autotuner for the time kernel (Algorithm 1) of an FP32 problem: times each
  * variant of the kernel the context would run for it on a probe of
  * n_probe_steps steps with the given particle count and stores the fastest

@@ -116,6 +116,8 @@ struct pm_ctx {
     int dir_bpc = 2;               // Dirichlet persistent blocks per CU (0 = occupancy)
     int dir_dump = 0;              // Dirichlet compaction (off): save waves with fewer live lanes
     int dir_launches = 8;          // ... over this many follow-up launches
+    int dir_tail = 4;              // cooperative disk tail: hand over waves with fewer live lanes
+    unsigned long long *tail_count = nullptr;  // walkers the last disk walk handed to the tail (device)
     void *pool = nullptr;          // compaction pools: counters, states, indices
     size_t pool_cap = 0;
     int engine = PM_ENGINE_AUTO;   // velocity engine of the FP32 torus time path
@@ -305,12 +307,13 @@ bool use_mx(const pm_ctx *c, const pm_problem *p)
 
 // FP64 fold, then the split-FP16 operands of the small-K matrix-core path.
 int fold_mx(pm_ctx *c, const pm_problem *p, const double *u, int n_sets, int64_t u_stride,
-            const unsigned char **out)
+            const unsigned char **out, const double **coef64 = nullptr)
 {
     double *coef;
     int64_t cs;
     int st = fold<double>(c, p, u, n_sets, u_stride, &coef, &cs);
     if (st) return st;
+    if (coef64) *coef64 = coef;
     st = ensure(c, &c->mx, &c->mx_cap, (size_t)n_sets * MX_SET_BYTES);
     if (st) return st;
     MxPackArgs pa{};
@@ -665,7 +668,8 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     T *coef = nullptr;
     int64_t cstride = 0;
     const unsigned char *mx_set = nullptr;
-    int st = mx ? fold_mx(c, p, u, 1, 2 * (int64_t)p->n_modes, &mx_set)
+    const double *coef64 = nullptr;
+    int st = mx ? fold_mx(c, p, u, 1, 2 * (int64_t)p->n_modes, &mx_set, &coef64)
                 : fold<T>(c, p, u, 1, 2 * (int64_t)p->n_modes, &coef, &cstride);
     if (st) return st;
     const int64_t total = np * n_obs;
@@ -731,9 +735,14 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
 
     // Compaction pools (two, used alternately): walkers saved by one launch
     // are dealt densely by the next; the last launch runs every walker out.
-    const int n_follow = c->dir_dump > 0 ? c->dir_launches : 0;
+    // The cooperative tail (matrix-core disk walk, sources without Gaussians)
+    // takes the place of the follow-up launches: one launch runs the saved
+    // walkers one per wave.
+    const bool tail = mx && fk <= 1 && c->dir_tail > 0;
+    const int n_follow = tail ? 0 : (c->dir_dump > 0 ? c->dir_launches : 0);
     DirPool pools[2] = {};
-    if (n_follow > 0) {
+    c->tail_count = nullptr;
+    if (n_follow > 0 || tail) {
         const int64_t cap = std::min<int64_t>(total, dirichlet_max_lanes(c->n_cu));
         const size_t st_bytes = (size_t)cap * DIR_POOL_WORDS * sizeof(double);
         const size_t ij_bytes = (size_t)cap * 2 * sizeof(uint32_t);
@@ -754,7 +763,7 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     if (mx && launch_check_disk_range(obs, n_obs, c->d_flags, c->stream) != hipSuccess) return PM_EDEVICE;
     PM_HIP(hipEventRecord(c->ev0, c->stream));
     a.mode = 0;
-    a.dump_below = n_follow > 0 ? c->dir_dump : 0;
+    a.dump_below = tail ? c->dir_tail : (n_follow > 0 ? c->dir_dump : 0);
     a.pout = pools[0];
     auto launch = [&]() -> hipError_t {
         if constexpr (std::is_same<T, float>::value) {
@@ -765,6 +774,21 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
         return launch_dirichlet<T>(a, p->K, fk, c->dir_src, c->n_cu, c->dir_bpc, p->domain, c->stream);
     };
     if (launch() != hipSuccess) return PM_EDEVICE;
+    if constexpr (std::is_same<T, float>::value) {
+        if (tail) {
+            a.mode = 1;
+            a.pin = pools[0];
+            a.dump_below = 0;
+            if (launch_pool_reset(pools[0].head, pools[1].count, c->stream) != hipSuccess) return PM_EDEVICE;
+            DiskTailConsts tc{};
+            tc.gdt = (float)(-dt * std::ldexp(1.0, MX_DISK_SHIFT));
+            tc.gauss = (float)(-2.0 * std::log(2.0) * (2.0 * kappa * dt) * std::ldexp(1.0, 2 * MX_DISK_SHIFT));
+            if (launch_dirichlet_tail(a, tc, coef64, row_stride(p->domain, p->K), p->K, fk, c->n_cu, c->stream) !=
+                hipSuccess)
+                return PM_EDEVICE;
+            c->tail_count = pools[0].count;
+        }
+    }
     for (int r = 1; r <= n_follow; ++r) {
         a.mode = 1;
         a.pin = pools[(r - 1) & 1];
@@ -1430,6 +1454,25 @@ int pm_set_dirichlet_compaction(pm_ctx *c, int dump_below, int launches)
     if (!c || c->closed || dump_below < 0 || dump_below > 64 || launches < 0 || launches > 64) return PM_EINVAL;
     c->dir_dump = dump_below;
     c->dir_launches = launches;
+    return PM_OK;
+}
+
+int pm_set_dirichlet_tail(pm_ctx *c, int live_below)
+{
+    if (!c || c->closed || live_below < 0 || live_below > 64) return PM_EINVAL;
+    c->dir_tail = live_below;
+    return PM_OK;
+}
+
+int pm_dirichlet_tail_walkers(pm_ctx *c, int64_t *walkers)
+{
+    if (!c || c->closed || !walkers) return PM_EINVAL;
+    *walkers = 0;
+    if (!c->tail_count) return PM_OK;
+    unsigned long long n = 0;
+    PM_HIP(hipMemcpyAsync(&n, c->tail_count, sizeof(n), hipMemcpyDeviceToHost, c->stream));
+    PM_HIP(hipStreamSynchronize(c->stream));
+    *walkers = (int64_t)n;
     return PM_OK;
 }
 

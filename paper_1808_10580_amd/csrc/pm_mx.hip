@@ -448,10 +448,9 @@ __device__ __forceinline__ void mx_velocity_disk(const h16x8 ahi, const h16x8 al
 // Torus coordinate as a 32-bit fraction of the period, position = X 2^-32:
 // the wrap is the modular overflow of the update.  The increment
 // -v dt + sqrt(2 kappa dt) z of eq. (euler) is formed in FP32 in units of
-// 2^-32 (constants pre-scaled by 2^32, dt split hi + lo so that its rounding
-// adds no coherent drift) and rounded to the nearest unit: 2.3e-10 per step,
-// below the FP32 velocity error.  The velocity is evaluated at the FP32 value
-// of the position in [-1/2, 1/2).
+// 2^-32 and added as a whole number of units (2.3e-10 of the period, below
+// the FP32 velocity error per step).  The velocity is evaluated at the FP32
+// value of the position in [-1/2, 1/2).
 // ---------------------------------------------------------------------------
 struct FixCoord {
     uint32_t X;
@@ -742,6 +741,133 @@ __global__ __launch_bounds__(256) void k_dirichlet_mx(const DirArgs<float> a, co
     });
 }
 
+// ---------------------------------------------------------------------------
+// The tail of Algorithm 2 on the disk.  Walkers that the matrix-core walk
+// saved to a pool (waves left with few live lanes once no fresh particle
+// remains) continue one per wave, the 64 lanes sharing each step.  Lane
+// 16 f + j (f = 0, 1, 2: the forms psi_F, F_x, F_y of disk_velocity; j < B)
+// holds column j of form f's coefficients in FP32 and forms
+// t = sum_i C_f[i][j] phi_i(x), times phi_j(y) = sin(2 pi (n_j y + ph_j)); a
+// row-wise DPP sum leaves the three forms in lanes 15, 31 and 47.  Lane l
+// draws the normals of Philox block b0 + l, so one draw serves 128 steps;
+// each step reads its pair with a wave-uniform lane index.  Steps, exit
+// test, source integral and cap are those of dirichlet_walk, every lane
+// holding the walker's state; lane 0 writes the exit record.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float row_shr_add(float v, int n)
+{
+    // v + (value of the lane n below in the same 16-lane row, 0 past its start)
+    int s = 0;
+    switch (n) {
+    case 1: s = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x111, 0xF, 0xF, true); break;
+    case 2: s = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x112, 0xF, 0xF, true); break;
+    case 4: s = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x114, 0xF, 0xF, true); break;
+    default: s = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x118, 0xF, 0xF, true); break;
+    }
+    return v + __builtin_bit_cast(float, s);
+}
+
+__device__ __forceinline__ float read_lane(float v, int l)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+template <int K, int FK>
+__global__ __launch_bounds__(256) void k_dirichlet_tail(const DirArgs<float> a, const DiskTailConsts tc,
+                                                        const double *__restrict__ coef, int row_stride)
+{
+    constexpr int B = 2 * K + 1;
+    static_assert(K >= 1 && B <= 16, "one 16-lane row per form");
+    const int lane = threadIdx.x & 63;
+    const int f = lane >> 4, j = lane & 15;
+    const bool act = f < 3 && j < B;
+    float c[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) c[i] = act ? (float)coef[j * row_stride + 3 * i + f] : 0.f;
+    const float nj = (float)((j + 1) >> 1), ph = (j & 1) ? 0.25f : 0.f;  // cos = sin shifted a quarter turn
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const int64_t count = (int64_t)uniform64((int64_t)*a.pin.count);
+    for (;;) {
+        unsigned long long tk = 0;
+        if (lane == 0) tk = atomicAdd(a.pin.head, 1ull);
+        const int64_t w_ix = uniform64((int64_t)__shfl(tk, 0));
+        if (w_ix >= count) break;
+        const double *S = a.pin.st + w_ix * DIR_POOL_WORDS;
+        DiskFix x, y;
+        x.load(S[0], S[1]);
+        y.load(S[2], S[3]);
+        double I = S[4];
+        int64_t n = (int64_t)S[5];
+        const uint32_t pi = a.pin.ij[2 * w_ix], pj = a.pin.ij[2 * w_ix + 1];
+        const int64_t t = (int64_t)pj * a.np + pi;
+        double xd = x.value(), yd = y.value();
+        float zr[4] = {0.f, 0.f, 0.f, 0.f};
+        int64_t b0 = INT64_MIN / 2;  // no block drawn yet
+        for (;;) {
+            const int64_t blk = n >> 1;
+            if (blk - b0 >= 64) {  // normals of blocks blk .. blk + 63, one per lane, in units
+                b0 = blk;
+                const U4 w = philox4x32_10((uint32_t)(b0 + lane), pi, pj, 0u, k0, k1);
+                box_muller_r2(w.x, w.y, tc.gauss, 0.f, 0.f, zr[0], zr[1]);
+                box_muller_r2(w.z, w.w, tc.gauss, 0.f, 0.f, zr[2], zr[3]);
+            }
+            const int src = (int)(blk - b0);
+            const bool second = (n & 1) != 0;
+            const float z0 = read_lane(second ? zr[2] : zr[0], src);
+            const float z1 = read_lane(second ? zr[3] : zr[1], src);
+
+            const float xs = x.at(), ys = y.at();
+            float px[B];
+            trig_basis<float, K>(xs, px);
+            float tj = c[0];
+#pragma unroll
+            for (int i = 1; i < B; ++i) tj = __builtin_fmaf(c[i], px[i], tj);
+            const float pyj = j == 0 ? 1.f : __builtin_amdgcn_sinf(__builtin_fmaf(nj, ys, ph));
+            float v = act ? tj * pyj : 0.f;
+            v = row_shr_add(v, 1);
+            v = row_shr_add(v, 2);
+            v = row_shr_add(v, 4);
+            v = row_shr_add(v, 8);
+            const float F0 = read_lane(v, 15), FX = read_lane(v, 31), FY = read_lane(v, 47);
+            const float wgt = 1.f - (xs * xs + ys * ys);
+            const float chi = wgt * wgt;
+            const float g4 = 4.f * wgt * F0;
+            const float vx = __builtin_fmaf(chi, FX, -(g4 * ys));
+            const float vy = __builtin_fmaf(chi, FY, g4 * xs);
+
+            // increment -dt v + noise in units of 2^-30, clamped to 1/2 as in
+            // the walk, truncated to a whole unit
+            DiskFix nx = x, ny = y;
+            nx.X += (int32_t)__builtin_fminf(__builtin_fmaxf(__builtin_fmaf(tc.gdt, vx + a.v0x, z0), -0x1p29f), 0x1p29f);
+            ny.X += (int32_t)__builtin_fminf(__builtin_fmaxf(__builtin_fmaf(tc.gdt, vy + a.v0y, z1), -0x1p29f), 0x1p29f);
+            I += source_at<FK>(a.f, xd, yd) * a.dtd;  // left point
+            n += 1;
+            const double nxd = nx.value(), nyd = ny.value();
+            const bool out = nxd * nxd + nyd * nyd >= 1.0;
+            if (out || n >= a.max_steps) {
+                double ex = nxd, ey = nyd;
+                if (out) {  // radial projection onto the circle
+                    const double r = sqrt(nxd * nxd + nyd * nyd);
+                    ex = nxd / r;
+                    ey = nyd / r;
+                }
+                if (lane == 0) {
+                    a.exitp[2 * t] = ex;
+                    a.exitp[2 * t + 1] = ey;
+                    a.integ[t] = I;
+                    a.nsteps[t] = (double)n;
+                    a.capped[t] = out ? 0 : 1;
+                }
+                break;
+            }
+            x = nx;
+            y = ny;
+            xd = nxd;
+            yd = nyd;
+        }
+    }
+}
+
 // Teacher-forced steps and velocity on the disk (the walk's fixed-point
 // coordinates, no wrap).
 template <int K>
@@ -863,6 +989,29 @@ hipError_t launch_step_mx(const MxStepArgs &a, int K, int domain, hipStream_t st
         }
         hipLaunchKernelGGL(k_step_mx<KK>, dim3((unsigned)blocks), dim3(256), 0, st, a);
         return hipGetLastError();
+    });
+}
+
+hipError_t launch_dirichlet_tail(const DirArgs<float> &a, const DiskTailConsts &tc, const double *coef,
+                                 int row_stride, int K, int fk, int n_cu, hipStream_t st)
+{
+    if (K < 1 || K > MX_MAX_K_DISK || (fk != 0 && fk != 1)) return hipErrorInvalidValue;
+    return dispatch_mx(K, [&](auto kc) -> hipError_t {
+        constexpr int KK = decltype(kc)::value;
+        if constexpr (KK > MX_MAX_K_DISK) {
+            return hipErrorInvalidValue;
+        } else {
+            void (*kern)(const DirArgs<float>, const DiskTailConsts, const double *, int) =
+                fk == 0 ? k_dirichlet_tail<KK, 0> : k_dirichlet_tail<KK, 1>;
+            int per_cu = 0;
+            hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
+            if (err != hipSuccess) return err;
+            if (per_cu < 1) per_cu = 1;
+            if (per_cu > 8) per_cu = 8;
+            // one wave per walker at a time; waves past the pool's count exit at once
+            hipLaunchKernelGGL(kern, dim3((unsigned)(per_cu * n_cu)), dim3(256), 0, st, a, tc, coef, row_stride);
+            return hipGetLastError();
+        }
     });
 }
 

@@ -279,6 +279,7 @@ def test_compaction_is_bitwise_neutral(pm, ctx, engine_of, prec, engine, dump, l
     """Saving tail walkers between launches and resuming them elsewhere changes
     nothing: every path, payoff, exit step and statistic is identical."""
     engine_of(engine)
+    ctx.set_dirichlet_tail(0)  # the compaction follow-ups, not the cooperative tail
     wl = W.dirichlet_main(n_particles=2000, prec=prec)
     prob = pm.Problem(ctx, "disk", wl.modes, prec=prec)
     res = []
@@ -289,9 +290,93 @@ def test_compaction_is_bitwise_neutral(pm, ctx, engine_of, prec, engine, dump, l
         assert ctx.sync() == pm.PM_OK
         res.append({k: np_(v).copy() for k, v in out.items()})
     ctx.set_dirichlet_compaction(0, 8)  # the default
+    ctx.set_dirichlet_tail(TAIL_DEFAULT)
     for k in res[0]:
         assert np.array_equal(res[0][k], res[1][k]), k
     prob.close()
+
+
+@pytest.fixture
+def tail_of(ctx):
+    """Set the cooperative-tail threshold for one test; the default is restored after."""
+    def use(live_below):
+        ctx.set_dirichlet_tail(live_below)
+        return live_below
+    yield use
+    ctx.set_dirichlet_tail(TAIL_DEFAULT)
+
+
+# the library's default threshold of the cooperative disk tail
+TAIL_DEFAULT = 4
+
+
+def _path_stats(P, ref):
+    same = P[..., 3].astype(np.int64) == ref["tau_steps"]
+    err = np.max(np.abs(P[..., :2][same] - ref["exit"][same]), axis=-1)
+    perr = np.abs(P[..., 2][same] - ref["payoff"][same])
+    return 1 - same.mean(), np.quantile(err, 0.99), np.quantile(perr, 0.99)
+
+
+@pytest.mark.parametrize("live_below", [64, 8])
+def test_tail_paths_match_oracle(pm, ctx, orc, engine_of, tail_of, live_below):
+    """Walkers handed to the cooperative tail (one walker per wave, the lanes
+    sharing each step) follow the oracle's paths as closely as the
+    matrix-core walk does: a flow at 1% strength and walks of a few thousand
+    steps (kappa 0.05), so that waves run the 1,024 iterations before a
+    hand-over and many walkers finish in the tail.  Against the oracle, the
+    run with the tail may differ in at most 1% more exit steps than the run
+    without it, and its exit point and payoff errors (p99, paths with equal
+    exit steps) stay within twice those of the run without it or 1e-5."""
+    engine_of("mfma")
+    stats = {}
+    ref = None
+    for lb in (0, live_below):
+        tail_of(lb)
+        out, st, r = _run_both(pm, ctx, orc, "fp32", Np=1000, kappa=0.05, scale=0.01)
+        ref = ref or r
+        assert st == pm.PM_OK
+        n_tail = ctx.dirichlet_tail_walkers()
+        stats[lb] = _path_stats(np_(out["paths"]), ref)
+        print("tail %d: %d walkers in the tail; different exit steps %.4f; exit point error p99 %.2e; "
+              "payoff error p99 %.2e" % ((lb, n_tail) + stats[lb]))
+        assert (n_tail > 0) == (lb > 0)
+    f0, e0, p0 = stats[0]
+    f1, e1, p1 = stats[live_below]
+    assert f1 <= f0 + 0.01
+    assert e1 <= max(2 * e0, 1e-5)
+    assert p1 <= max(2 * p0, 1e-5)
+
+
+def test_tail_capped_walkers_and_sources(pm, ctx, orc, engine_of, tail_of):
+    """A cap reached inside the tail is reported as in the walk (payoff -int f
+    along the path, counted by pm_sync); a linear source is integrated at the
+    left point of every step.  Compared with the oracle as the run without
+    the tail is."""
+    engine_of("mfma")
+    f = W.fld("linear", [1.0, -0.5, 0.25])
+    stats = {}
+    for lb in (0, 64):
+        tail_of(lb)
+        out, st, ref = _run_both(pm, ctx, orc, "fp32", Np=300, kappa=0.01, max_steps=3000, f=f, scale=0.01)
+        n_tail = ctx.dirichlet_tail_walkers()
+        n_cap = int(np.sum(np_(out["n_capped"])))
+        stats[lb] = _path_stats(np_(out["paths"]), ref)
+        print("tail %d with cap 3000: %d walkers in the tail, %d capped (oracle %d); different exit steps %.4f; "
+              "payoff error p99 %.2e" % (lb, n_tail, n_cap, int(ref["capped"].sum()), stats[lb][0], stats[lb][2]))
+        assert st == pm.PM_ECAPPED
+        assert ctx.sync() == pm.PM_OK
+        assert (n_tail > 0) == (lb > 0)
+        assert ref["capped"].sum() > 0
+        assert abs(n_cap - int(ref["capped"].sum())) <= max(2, 0.02 * ref["capped"].sum())
+    assert stats[64][0] <= stats[0][0] + 0.01
+    assert stats[64][2] <= max(2 * stats[0][2], 1e-5)
+
+
+def test_tail_setting_range(pm, ctx):
+    for bad in (-1, 65):
+        with pytest.raises(pm.PMError):
+            ctx.set_dirichlet_tail(bad)
+    ctx.set_dirichlet_tail(TAIL_DEFAULT)
 
 
 def test_compaction_keeps_source_integrals(pm, ctx):
