@@ -537,6 +537,56 @@ def bench_pcn(args):
     print(json.dumps(out))
 
 
+def mlp_train_flops(d_in: int, h: int, L: int, d_out: int, n: int) -> int:
+    """Matrix-product FLOPs of one training step of the surrogate MLP (batch n,
+    FMA = 2): the forward products, the weight gradients (the same shapes) and
+    the input gradients of every layer but the first."""
+    shapes = [(d_in, h)] + [(h, h)] * (L - 1) + [(h, d_out)]
+    fwd = sum(2 * n * a * b for a, b in shapes)
+    dx = sum(2 * n * a * b for a, b in shapes[1:])
+    return 2 * fwd + dx
+
+
+def bench_mlp(args):
+    """Adam steps/s of the surrogate MLP (168 -> 512 x 3 -> 49, batch 1,024:
+    the shape the delayed-acceptance study trains), and its matrix products'
+    rate against the dense BF16 peak.  Timed over --steps blocks of 100
+    training steps on synthetic standardised data; the rate includes the
+    launch gaps between the step's kernels (their own durations: rocprofv3)."""
+    import numpy as np
+    import torch
+    import paper_1808_10580_amd as pm
+
+    d_in, h, L, d_out, n = 168, 512, 3, 49, 1024
+    ctx = pm.Context(0)
+    net = pm.MLP(ctx, d_in, h, L, d_out, n, seed=5)
+    rng = np.random.default_rng(1808)
+    dev = ctx.device
+    X = torch.tensor(rng.standard_normal((n, d_in)), dtype=torch.float32, device=dev)
+    T = torch.tensor(rng.standard_normal((n, d_out)), dtype=torch.float32, device=dev)
+    per_block = 100
+    for _ in range(args.warmup * per_block):
+        net.train_step(X, T, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps * per_block):
+        net.train_step(X, T, 1e-4)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    n_steps = args.steps * per_block
+    fl = mlp_train_flops(d_in, h, L, d_out, n)
+    tf = fl * n_steps / sec / 1e12
+    out = {"metric": "surrogate MLP training steps/s", "value": n_steps / sec, "unit": "steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * sec / n_steps,
+           "higher_is_better": True, "vs_baseline": None, "dtype": "bf16 x bf16 -> fp32", "data": "synthetic",
+           "config": {"workload": f"mlp-train: {d_in} -> {h} x {L} -> {d_out}, GELU, batch {n}, Adam, "
+                                  f"{per_block} steps per timed block"},
+           "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP16_DENSE_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(tf / PEAK_FP16_DENSE_TFLOPS, 5), "traffic": None,
+                        "flop_per_step": fl, "note": "wall time of whole training steps (launch gaps included)"}}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -562,7 +612,7 @@ def main():
                     help="velocity engine of FP32 problems (auto = matrix cores for torus K <= 8, disk K <= 4)")
     ap.add_argument("--workload", default="torus-k6-fp32",
                     help="torus-k6-fp32 (the benchmark line), torus-k80-turbulent, disk-dirichlet, torus-k6-batch, "
-                         "torus-modes-sweep, pcn (with --model)")
+                         "torus-modes-sweep, pcn (with --model), mlp-train")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -572,6 +622,9 @@ def main():
         sys.exit(2)
     if args.workload == "torus-modes-sweep":
         bench_modes_sweep(args)
+        return
+    if args.workload == "mlp-train":
+        bench_mlp(args)
         return
     if args.workload == "pcn":
         bench_pcn(args)

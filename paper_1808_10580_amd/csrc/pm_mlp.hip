@@ -8,9 +8,13 @@
 // holds C[rows 4(l/16)..+3][col l%16].  op(A) = A or A^T and op(B) = B or B^T
 // cover the forward products H W, the input gradients dZ W^T and the weight
 // gradients H^T dZ.  Epilogues fuse bias + GELU (forward) and the GELU
-// derivative (backward).
+// derivative (backward).  A product whose K exceeds SPLIT_KC is split along K
+// (partial products in scratch, added in order by k_split_epilogue, which
+// then applies the epilogue), so that the small products of the surrogate
+// still spread over the chip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -42,6 +46,11 @@ struct GemmArgs {
     int ldh;
     const float *Z;  // saved pre-activation for EPI_GELU_GRAD
     int ldz;
+    // split K: block z of the grid reduces k in [z kc, (z + 1) kc) into
+    // C + z c_split (plain products; gemm() sets these, kc = 0: all of K)
+    int kc;
+    int64_t c_split;
+    float *part;  // scratch for split-K partial products (nullptr: no split)
 };
 
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
@@ -61,6 +70,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs g)
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int bm = blockIdx.y * TM, bn = blockIdx.x * TN;
+    const int kb = g.kc ? (int)blockIdx.z * g.kc : 0;
+    const int ke = g.kc ? (kb + g.kc < g.K ? kb + g.kc : g.K) : g.K;
+    float *const C = g.C + (int64_t)blockIdx.z * g.c_split;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
     f32x4 acc[2][2];
 #pragma unroll
@@ -69,7 +81,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs g)
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16 zero = (bf16)0.0f;
 
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
+    for (int k0 = kb; k0 < ke; k0 += TK) {
         // op(A)(m, k) -> As[m][k]; the fastest-varying thread index follows
         // the contiguous global dimension.
         for (int e = tid; e < TM * TK; e += 256) {
@@ -78,7 +90,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs g)
             else { kk = e / TM; r = e % TM; }
             const int m = bm + r, k = k0 + kk;
             bf16 v = zero;
-            if (m < g.M && k < g.K) v = TA ? g.A[(int64_t)k * g.lda + m] : g.A[(int64_t)m * g.lda + k];
+            if (m < g.M && k < ke) v = TA ? g.A[(int64_t)k * g.lda + m] : g.A[(int64_t)m * g.lda + k];
             As[r][kk] = v;
         }
         // op(B)(k, n) -> Bs[n][k]
@@ -88,7 +100,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs g)
             else { c = e / TK; kk = e % TK; }
             const int n = bn + c, k = k0 + kk;
             bf16 v = zero;
-            if (n < g.N && k < g.K) v = TB ? g.B[(int64_t)n * g.ldb + k] : g.B[(int64_t)k * g.ldb + n];
+            if (n < g.N && k < ke) v = TB ? g.B[(int64_t)n * g.ldb + k] : g.B[(int64_t)k * g.ldb + n];
             Bs[c][kk] = v;
         }
         __syncthreads();
@@ -117,24 +129,74 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs g)
                 float v = acc[a][b][i];
                 if (EPI == EPI_STORE) {
                     if (g.bias) v += g.bias[n];
-                    g.C[(int64_t)m * g.ldc + n] = v;
+                    C[(int64_t)m * g.ldc + n] = v;
                 } else if (EPI == EPI_BIAS_GELU) {
                     v += g.bias[n];
-                    g.C[(int64_t)m * g.ldc + n] = v;
+                    C[(int64_t)m * g.ldc + n] = v;
                     g.H[(int64_t)m * g.ldh + n] = (bf16)gelu(v);
                 } else {
                     v *= gelu_grad(g.Z[(int64_t)m * g.ldz + n]);
-                    g.C[(int64_t)m * g.ldc + n] = v;
+                    C[(int64_t)m * g.ldc + n] = v;
                     g.H[(int64_t)m * g.ldh + n] = (bf16)v;
                 }
             }
 }
 
-template <bool TA, bool TB, int EPI>
-static hipError_t gemm(const GemmArgs &g, hipStream_t st)
+// K chunk of split products (a multiple of the K tile).  A product whose K
+// exceeds it runs as ceil(K / SPLIT_KC) blocks along z writing plain partial
+// products to scratch; k_split_epilogue then adds them in order of z and
+// applies the epilogue.  Results do not depend on scheduling.
+constexpr int SPLIT_KC = 128;
+
+template <int EPI>
+__global__ void k_split_epilogue(const GemmArgs g, int splits)
 {
-    dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM);
-    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, st, g);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t count = (int64_t)g.M * g.N;
+    if (i >= count) return;
+    const int m = (int)(i / g.N), n = (int)(i - (int64_t)m * g.N);
+    float v = g.part[i];
+    for (int z = 1; z < splits; ++z) v += g.part[(int64_t)z * count + i];
+    if (EPI == EPI_STORE) {
+        if (g.bias) v += g.bias[n];
+        g.C[(int64_t)m * g.ldc + n] = v;
+    } else if (EPI == EPI_BIAS_GELU) {
+        v += g.bias[n];
+        g.C[(int64_t)m * g.ldc + n] = v;
+        g.H[(int64_t)m * g.ldh + n] = (bf16)gelu(v);
+    } else {
+        v *= gelu_grad(g.Z[(int64_t)m * g.ldz + n]);
+        g.C[(int64_t)m * g.ldc + n] = v;
+        g.H[(int64_t)m * g.ldh + n] = (bf16)v;
+    }
+}
+
+static int split_count(int K) { return (K + SPLIT_KC - 1) / SPLIT_KC; }
+
+template <bool TA, bool TB, int EPI>
+static hipError_t gemm(const GemmArgs &g0, hipStream_t st)
+{
+    const int splits = g0.part ? split_count(g0.K) : 1;
+    if (splits <= 1) {
+        GemmArgs g = g0;
+        g.kc = 0;
+        g.c_split = 0;
+        dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, 1);
+        hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, st, g);
+        return hipGetLastError();
+    }
+    GemmArgs p = g0;  // partial products into scratch, M x N each
+    p.C = g0.part;
+    p.ldc = g0.N;
+    p.bias = nullptr;
+    p.kc = SPLIT_KC;
+    p.c_split = (int64_t)g0.M * g0.N;
+    dim3 grid((p.N + TN - 1) / TN, (p.M + TM - 1) / TM, splits);
+    hipLaunchKernelGGL((k_gemm<TA, TB, EPI_STORE>), grid, dim3(256), 0, st, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t count = (int64_t)g0.M * g0.N;
+    hipLaunchKernelGGL((k_split_epilogue<EPI>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, g0, splits);
     return hipGetLastError();
 }
 
@@ -177,14 +239,44 @@ __global__ void k_loss_grad(const float *__restrict__ y, const float *__restrict
     if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, contrib);
 }
 
-// db[j] = sum_m dz[m][j]
-__global__ void k_colsum(const float *__restrict__ dz, int n, int d, float *__restrict__ db)
+// db[j] = sum_m dz[m][j] in two passes.  k_colsum: block (x, r) takes 64
+// columns and rows r, r + CS_CHUNKS, ...; thread (g, c) of its 1024 sums
+// every CS_GROUPS-th of those rows of column c (coalesced rows of 64 floats
+// per wave) and the 16 row groups are added in a fixed order through LDS into
+// part[r][j].  k_colsum_rows adds the CS_CHUNKS partial rows in order.  The
+// result does not depend on scheduling.
+constexpr int CS_COLS = 64, CS_GROUPS = 16, CS_CHUNKS = 16;
+__global__ __launch_bounds__(1024) void k_colsum(const float *__restrict__ dz, int n, int d,
+                                                 float *__restrict__ part)
+{
+    __shared__ float acc[CS_GROUPS][CS_COLS];
+    const int c = threadIdx.x & (CS_COLS - 1), g = threadIdx.x / CS_COLS;
+    const int j = blockIdx.x * CS_COLS + c, r = blockIdx.y;
+    float s0 = 0.f, s1 = 0.f;
+    if (j < d) {
+        int m = r + CS_CHUNKS * g;
+        for (; m + CS_CHUNKS * CS_GROUPS < n; m += 2 * CS_CHUNKS * CS_GROUPS) {
+            s0 += dz[(int64_t)m * d + j];
+            s1 += dz[(int64_t)(m + CS_CHUNKS * CS_GROUPS) * d + j];
+        }
+        if (m < n) s0 += dz[(int64_t)m * d + j];
+    }
+    acc[g][c] = s0 + s1;
+    __syncthreads();
+    if (g == 0 && j < d) {
+        float t = 0.f;
+        for (int q = 0; q < CS_GROUPS; ++q) t += acc[q][c];
+        part[(int64_t)r * d + j] = t;
+    }
+}
+
+__global__ void k_colsum_rows(const float *__restrict__ part, int d, float *__restrict__ db)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= d) return;
-    float s = 0.f;
-    for (int m = 0; m < n; ++m) s += dz[(int64_t)m * d + j];
-    db[j] = s;
+    float t = 0.f;
+    for (int r = 0; r < CS_CHUNKS; ++r) t += part[(int64_t)r * d + j];
+    db[j] = t;
 }
 
 __global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m1,
@@ -235,6 +327,7 @@ struct pm_mlp {
     bf16 *dYb = nullptr;
     float *dZ[2] = {nullptr, nullptr};
     bf16 *dZb[2] = {nullptr, nullptr};
+    float *part = nullptr;  // split-K partial weight gradients
     int64_t step = 0;
     std::vector<void *> allocs;
 };
@@ -272,6 +365,7 @@ int forward_impl(pm_mlp *m, const float *x, int n, hipStream_t st)
         a.B = m->ws + m->offW[l];
         a.ldb = m->Nd[l];
         a.bias = m->w + m->offB[l];
+        a.part = m->part;
         if (l < m->L) {
             a.C = m->Z[l + 1];
             a.ldc = m->h;
@@ -310,10 +404,13 @@ int grads_impl(pm_mlp *m, const float *x, const float *t, int n, float *loss, hi
         a.lda = K;
         a.B = dzb;
         a.ldb = N;
-        a.C = m->g + m->offW[l];
         a.ldc = N;
+        a.C = m->g + m->offW[l];
+        a.part = m->part;
         if (gemm<true, false, EPI_STORE>(a, st) != hipSuccess) return PM_EDEVICE;
-        hipLaunchKernelGGL(k_colsum, g1(N), dim3(256), 0, st, dz, n, N, m->g + m->offB[l]);
+        hipLaunchKernelGGL(k_colsum, dim3((N + CS_COLS - 1) / CS_COLS, CS_CHUNKS), dim3(CS_COLS * CS_GROUPS), 0, st,
+                           dz, n, N, m->part);
+        hipLaunchKernelGGL(k_colsum_rows, g1(N), dim3(256), 0, st, m->part, N, m->g + m->offB[l]);
         if (l == 0) break;
         // dZ_{l} (input side) = (dZ W_l^T) * GELU'(Z_l)
         GemmArgs b{};
@@ -330,6 +427,7 @@ int grads_impl(pm_mlp *m, const float *x, const float *t, int n, float *loss, hi
         b.ldh = K;
         b.Z = m->Z[l];
         b.ldz = K;
+        b.part = m->part;
         if (gemm<false, true, EPI_GELU_GRAD>(b, st) != hipSuccess) return PM_EDEVICE;
         dz = m->dZ[cur];
         dzb = m->dZb[cur];
@@ -399,6 +497,20 @@ int pm_mlp_create(pm_ctx *ctx, int d_in, int d_hidden, int n_hidden, int d_out, 
     for (int i = 0; i < 2; ++i) {
         A((void **)&m->dZ[i], (size_t)max_batch * wmax * 4);
         A((void **)&m->dZb[i], (size_t)max_batch * wmax * 2);
+    }
+    {
+        // split-K scratch: the largest splits x M x N over the products of a
+        // training step (forward H W, weight gradients H^T dZ, input
+        // gradients dZ W^T)
+        int64_t need = 1;
+        for (int l = 0; l <= n_hidden; ++l) {
+            const int64_t k = l == 0 ? d_in : d_hidden, nn = l == n_hidden ? d_out : d_hidden;
+            need = std::max<int64_t>(need, split_count((int)k) * (int64_t)max_batch * nn);
+            need = std::max<int64_t>(need, split_count(max_batch) * k * nn);
+            if (l > 0) need = std::max<int64_t>(need, split_count((int)nn) * (int64_t)max_batch * k);
+        }
+        need = std::max<int64_t>(need, (int64_t)CS_CHUNKS * std::max(d_hidden, d_out));  // column sums
+        A((void **)&m->part, (size_t)need * 4);
     }
     if (st) {
         mlp_free(m);
