@@ -230,6 +230,7 @@ StepConsts<T> step_consts(double dt, double kappa)
     c.dth = (T)dt;
     c.dtl = (T)(dt - (double)c.dth);
     c.sq = (T)std::sqrt(2.0 * kappa * dt);
+    c.g2 = (T)0;  // unused by the floating-point coordinates
     return c;
 }
 
@@ -241,6 +242,7 @@ StepConsts<float> fixed_consts(double dt, double kappa, double S = 4294967296.0)
     c.dth = (float)(dt * S);
     c.dtl = (float)(dt * S - (double)c.dth);
     c.sq = (float)(std::sqrt(2.0 * kappa * dt) * S);
+    c.g2 = (float)(-2.0 * std::log(2.0) * (2.0 * kappa * dt) * S * S);
     return c;
 }
 
@@ -620,7 +622,7 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
             MxTimeArgs ma{};
             ma.t = a;
             ma.fx = fixed_consts(dte, kappa);
-            ma.gauss = (float)(-2.0 * std::log(2.0) * (2.0 * kappa * dte) * 0x1p64);
+            ma.gauss = ma.fx.g2;
             ma.sets = mx_sets;
             ma.vmax_fast = (float)((0.45 - 5.9 * std::sqrt(2.0 * kappa * dte)) / dte -
                                    std::max(std::fabs(p->v0[0]), std::fabs(p->v0[1])));
@@ -780,11 +782,8 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
             a.pin = pools[0];
             a.dump_below = 0;
             if (launch_pool_reset(pools[0].head, pools[1].count, c->stream) != hipSuccess) return PM_EDEVICE;
-            DiskTailConsts tc{};
-            tc.gdt = (float)(-dt * std::ldexp(1.0, MX_DISK_SHIFT));
-            tc.gauss = (float)(-2.0 * std::log(2.0) * (2.0 * kappa * dt) * std::ldexp(1.0, 2 * MX_DISK_SHIFT));
-            if (launch_dirichlet_tail(a, tc, coef64, row_stride(p->domain, p->K), p->K, fk, c->n_cu, c->stream) !=
-                hipSuccess)
+            if (launch_dirichlet_tail(a, fixed_consts(dt, kappa, std::ldexp(1.0, MX_DISK_SHIFT)), coef64,
+                                      row_stride(p->domain, p->K), p->K, fk, c->n_cu, c->stream) != hipSuccess)
                 return PM_EDEVICE;
             c->tail_count = pools[0].count;
         }

@@ -199,6 +199,7 @@ __device__ __forceinline__ void trig_basis(T s, T *phi)
 template <typename T>
 struct StepConsts {
     T dth, dtl, sq;
+    T g2;  // fixed-point walks: -2 ln 2 sq^2, Box-Muller normals come out times sq
 };
 
 template <typename T>
@@ -207,6 +208,11 @@ struct Coord;
 template <>
 struct Coord<double> {
     double v;
+    static __device__ __forceinline__ void normals(uint32_t wa, uint32_t wb, const StepConsts<double> &, double &z0,
+                                                   double &z1)
+    {
+        box_muller(wa, wb, z0, z1);
+    }
     __device__ __forceinline__ void set(double x) { v = x; }
     __device__ __forceinline__ double at() const { return v; }
     __device__ __forceinline__ double value() const { return v; }
@@ -227,6 +233,11 @@ struct Coord<double> {
 template <>
 struct Coord<float> {
     float hi, lo;
+    static __device__ __forceinline__ void normals(uint32_t wa, uint32_t wb, const StepConsts<float> &, float &z0,
+                                                   float &z1)
+    {
+        box_muller(wa, wb, z0, z1);
+    }
     __device__ __forceinline__ void set(double x)
     {
         hi = (float)x;

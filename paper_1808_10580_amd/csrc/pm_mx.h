@@ -160,11 +160,7 @@ hipError_t launch_dirichlet_mx(const DirArgs<float> &a, const StepConsts<float> 
 // The cooperative tail: walkers of a.pin (head reset to 0) run to their exit
 // one per wave; coef = the FP64 disk coefficients of k_fold (row j at
 // j * row_stride: Psi, Cx, Cy of entry i at 3i..3i+2).
-struct DiskTailConsts {
-    float gdt;    // -dt 2^MX_DISK_SHIFT
-    float gauss;  // -2 ln 2 (2 kappa dt) 2^(2 MX_DISK_SHIFT): normals come out in units
-};
-hipError_t launch_dirichlet_tail(const DirArgs<float> &a, const DiskTailConsts &tc, const double *coef,
+hipError_t launch_dirichlet_tail(const DirArgs<float> &a, const StepConsts<float> &fx, const double *coef,
                                  int row_stride, int K, int fk, int n_cu, hipStream_t st);
 
 }  // namespace pm

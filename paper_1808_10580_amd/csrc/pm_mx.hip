@@ -485,24 +485,29 @@ struct FixCoord {
 };
 
 // Disk coordinate as a signed 32-bit multiple of 2^-30 (range +-2): the
-// increment of eq. (euler) is formed as on the torus in units of 2^-30 and
-// rounded to the nearest unit (9.3e-10, unbiased, below the FP32 velocity
-// error per step).  Each increment is clamped to 1/2, so a walker that starts
-// a step inside the unit disk stays inside +-1.5 and the coordinate never
-// wraps; only steps that would move a particle by more than half the radius,
-// far outside any usable time step, are affected.  The exit test reads the
-// exact FP64 value.
+// increment -v dt + sqrt(2 kappa dt) z of eq. (euler) is formed in FP32 in
+// units of 2^-30 as one FMA (the normals come from `normals` already times
+// sqrt(2 kappa dt) 2^30; dt 2^30 rounded once to FP32) and added as a whole
+// number of units, truncated (9.3e-10, below the FP32 velocity error per
+// step).  Each increment is clamped to 1/2, so a walker that starts a step
+// inside the unit disk stays inside +-1.5 and the coordinate never wraps;
+// only steps that would move a particle by more than half the radius, far
+// outside any usable time step, are affected.  The exit test reads the exact
+// FP64 value.
 struct DiskFix {
     int32_t X;
+    static __device__ __forceinline__ void normals(uint32_t wa, uint32_t wb, const StepConsts<float> &c, float &z0,
+                                                   float &z1)
+    {
+        box_muller_r2(wa, wb, c.g2, 0.f, 0.f, z0, z1);
+    }
     __device__ __forceinline__ void set(double x) { X = (int32_t)llrint(x * 0x1p30); }
     __device__ __forceinline__ float at() const { return (float)X * 0x1p-30f; }
     __device__ __forceinline__ double value() const { return (double)X * 0x1p-30; }
-    __device__ __forceinline__ void advance(float vel, float z, const StepConsts<float> &c)
+    __device__ __forceinline__ void advance(float vel, float zs, const StepConsts<float> &c)
     {
-        float d = __builtin_fmaf(-c.dtl, vel, c.sq * z);
-        d = __builtin_fmaf(-c.dth, vel, d);
-        d = __builtin_fminf(__builtin_fmaxf(d, -0x1p29f), 0x1p29f);
-        X += (int32_t)__builtin_rintf(d);
+        const float d = __builtin_fmaf(-c.dth, vel, zs);
+        X += (int32_t)__builtin_fminf(__builtin_fmaxf(d, -0x1p29f), 0x1p29f);
     }
     __device__ __forceinline__ void save(double &a, double &b) const
     {
@@ -750,9 +755,10 @@ __global__ __launch_bounds__(256) void k_dirichlet_mx(const DirArgs<float> a, co
 // t = sum_i C_f[i][j] phi_i(x), times phi_j(y) = sin(2 pi (n_j y + ph_j)); a
 // row-wise DPP sum leaves the three forms in lanes 15, 31 and 47.  Lane l
 // draws the normals of Philox block b0 + l, so one draw serves 128 steps;
-// each step reads its pair with a wave-uniform lane index.  Steps, exit
-// test, source integral and cap are those of dirichlet_walk, every lane
-// holding the walker's state; lane 0 writes the exit record.
+// each step reads its pair with a wave-uniform lane index.  Normals,
+// update, exit test, source integral and cap are those of dirichlet_walk with
+// DiskFix, every lane holding the walker's state; lane 0 writes the exit
+// record.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float row_shr_add(float v, int n)
 {
@@ -773,7 +779,7 @@ __device__ __forceinline__ float read_lane(float v, int l)
 }
 
 template <int K, int FK>
-__global__ __launch_bounds__(256) void k_dirichlet_tail(const DirArgs<float> a, const DiskTailConsts tc,
+__global__ __launch_bounds__(256) void k_dirichlet_tail(const DirArgs<float> a, const StepConsts<float> fx,
                                                         const double *__restrict__ coef, int row_stride)
 {
     constexpr int B = 2 * K + 1;
@@ -808,8 +814,8 @@ __global__ __launch_bounds__(256) void k_dirichlet_tail(const DirArgs<float> a, 
             if (blk - b0 >= 64) {  // normals of blocks blk .. blk + 63, one per lane, in units
                 b0 = blk;
                 const U4 w = philox4x32_10((uint32_t)(b0 + lane), pi, pj, 0u, k0, k1);
-                box_muller_r2(w.x, w.y, tc.gauss, 0.f, 0.f, zr[0], zr[1]);
-                box_muller_r2(w.z, w.w, tc.gauss, 0.f, 0.f, zr[2], zr[3]);
+                DiskFix::normals(w.x, w.y, fx, zr[0], zr[1]);
+                DiskFix::normals(w.z, w.w, fx, zr[2], zr[3]);
             }
             const int src = (int)(blk - b0);
             const bool second = (n & 1) != 0;
@@ -835,11 +841,9 @@ __global__ __launch_bounds__(256) void k_dirichlet_tail(const DirArgs<float> a, 
             const float vx = __builtin_fmaf(chi, FX, -(g4 * ys));
             const float vy = __builtin_fmaf(chi, FY, g4 * xs);
 
-            // increment -dt v + noise in units of 2^-30, clamped to 1/2 as in
-            // the walk, truncated to a whole unit
-            DiskFix nx = x, ny = y;
-            nx.X += (int32_t)__builtin_fminf(__builtin_fmaxf(__builtin_fmaf(tc.gdt, vx + a.v0x, z0), -0x1p29f), 0x1p29f);
-            ny.X += (int32_t)__builtin_fminf(__builtin_fmaxf(__builtin_fmaf(tc.gdt, vy + a.v0y, z1), -0x1p29f), 0x1p29f);
+            DiskFix nx = x, ny = y;  // the walk's update
+            nx.advance(vx + a.v0x, z0, fx);
+            ny.advance(vy + a.v0y, z1, fx);
             I += source_at<FK>(a.f, xd, yd) * a.dtd;  // left point
             n += 1;
             const double nxd = nx.value(), nyd = ny.value();
@@ -897,8 +901,8 @@ __global__ __launch_bounds__(256) void k_step_mx_disk(const MxStepArgs a)
     const uint64_t n = a.n[e];
     const U4 w = philox4x32_10((uint32_t)(n >> 1), a.i[e], a.j[e], 0u, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
     float z0, z1;
-    if ((n & 1) == 0) box_muller(w.x, w.y, z0, z1);
-    else box_muller(w.z, w.w, z0, z1);
+    if ((n & 1) == 0) DiskFix::normals(w.x, w.y, a.fx, z0, z1);
+    else DiskFix::normals(w.z, w.w, a.fx, z0, z1);
     x.advance(vx + a.v0x, z0, a.fx);
     y.advance(vy + a.v0y, z1, a.fx);
     a.Y[2 * e] = x.value();
@@ -992,7 +996,7 @@ hipError_t launch_step_mx(const MxStepArgs &a, int K, int domain, hipStream_t st
     });
 }
 
-hipError_t launch_dirichlet_tail(const DirArgs<float> &a, const DiskTailConsts &tc, const double *coef,
+hipError_t launch_dirichlet_tail(const DirArgs<float> &a, const StepConsts<float> &fx, const double *coef,
                                  int row_stride, int K, int fk, int n_cu, hipStream_t st)
 {
     if (K < 1 || K > MX_MAX_K_DISK || (fk != 0 && fk != 1)) return hipErrorInvalidValue;
@@ -1001,7 +1005,7 @@ hipError_t launch_dirichlet_tail(const DirArgs<float> &a, const DiskTailConsts &
         if constexpr (KK > MX_MAX_K_DISK) {
             return hipErrorInvalidValue;
         } else {
-            void (*kern)(const DirArgs<float>, const DiskTailConsts, const double *, int) =
+            void (*kern)(const DirArgs<float>, const StepConsts<float>, const double *, int) =
                 fk == 0 ? k_dirichlet_tail<KK, 0> : k_dirichlet_tail<KK, 1>;
             int per_cu = 0;
             hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
@@ -1009,7 +1013,7 @@ hipError_t launch_dirichlet_tail(const DirArgs<float> &a, const DiskTailConsts &
             if (per_cu < 1) per_cu = 1;
             if (per_cu > 8) per_cu = 8;
             // one wave per walker at a time; waves past the pool's count exit at once
-            hipLaunchKernelGGL(kern, dim3((unsigned)(per_cu * n_cu)), dim3(256), 0, st, a, tc, coef, row_stride);
+            hipLaunchKernelGGL(kern, dim3((unsigned)(per_cu * n_cu)), dim3(256), 0, st, a, fx, coef, row_stride);
             return hipGetLastError();
         }
     });

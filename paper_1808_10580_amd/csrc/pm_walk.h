@@ -190,8 +190,8 @@ __device__ __forceinline__ void dirichlet_walk(const DirArgs<T> &a, const StepCo
         ++iters;
         const U4 w = philox4x32_10((uint32_t)(n >> 1), pi, pj, 0u, k0, k1);
         T z0, z1, z2, z3;
-        box_muller(w.x, w.y, z0, z1);
-        box_muller(w.z, w.w, z2, z3);
+        C::normals(w.x, w.y, sc, z0, z1);
+        C::normals(w.z, w.w, sc, z2, z3);
         substep(z0, z1);
         substep(z2, z3);
     }
