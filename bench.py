@@ -44,8 +44,8 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 COUNTER_TRAFFIC = {
     # k_time<float,6,3>: FETCH 157.25 KiB x 2 + WRITE 77,480.78 KiB x 1
     "valu": (79_662_368, "3b284018099e00ed8b8ca29fbfcbd81e7f33371ba6f8cff6f3ffc09d0a75e464"),
-    # k_time_mx<6>: FETCH 62.19 KiB x 2 + WRITE 79,140.34 KiB x 1
-    "mfma": (81_166_818, "4560017ae817a31034137823e406a326421112bc992b80ba16825dfa1df1f047"),
+    # k_time_mx<6>: FETCH 61.25 KiB x 2 + WRITE 79,140.34 KiB x 1
+    "mfma": (81_164_899, "0530b6f39824c7aa0375c9caa73ffc08a9c498db35718de461ca32a2414e19b4"),
 }
 # The same for the dominant kernel of the other workloads (bench.py
 # --workload ...), keyed by (workload, velocity engine): (bytes per launch,
@@ -53,8 +53,9 @@ COUNTER_TRAFFIC = {
 OTHER_TRAFFIC = {
     # k_time_hk<6,2>: FETCH 918.69 KiB x 2 + WRITE 40,702.84 KiB x 1
     ("torus-k80-turbulent", "mfma"): (43_561_184, "310429af8df2502301e9988b4708f97f143cd342e07191f62799a99be583c96b", "hk"),
-    # k_dirichlet_mx<4,0>: FETCH 75.94 KiB x 2 + WRITE 185,324.66 KiB x 1
-    ("disk-dirichlet", "mfma"): (189_927_968, "828d8732ecab75f83943076e30c4f5e0ec6dfedd5862b993f1f392e005e9b5e1", "mfma"),
+    # k_dirichlet_mx<4,0> (the map's first launch; the cooperative tail adds FETCH 567 KiB x 2 +
+    # WRITE 1,205 KiB): FETCH 74.44 KiB x 2 + WRITE 184,737 KiB x 1
+    ("disk-dirichlet", "mfma"): (189_323_131, "0530b6f39824c7aa0375c9caa73ffc08a9c498db35718de461ca32a2414e19b4", "mfma"),
     # k_dirichlet<float,4,0,SC>: FETCH 90.13 KiB x 2 + WRITE 185,431.22 KiB x 1
     ("disk-dirichlet", "valu"): (190_066_144, "3b284018099e00ed8b8ca29fbfcbd81e7f33371ba6f8cff6f3ffc09d0a75e464", "valu"),
 }
@@ -82,9 +83,9 @@ PEAK_FP16_DENSE_TFLOPS = 2500.0
 # kernel's cycles per SIMD).
 COUNTERS = {
     "mfma": ({"valu_insts": 130.1, "valu_slots": 164.1, "fma_f32": 47.0, "mul_f32": 6.0, "add_f32": 4.0,
-              "issue_frac": 1.03, "mfma_busy": 0.301,
+              "issue_frac": 1.03, "mfma_busy": 0.302,
               "source": "profiles/k_time_mx_torus-k6-fp32_pmc.md"},
-             "4560017ae817a31034137823e406a326421112bc992b80ba16825dfa1df1f047"),
+             "0530b6f39824c7aa0375c9caa73ffc08a9c498db35718de461ca32a2414e19b4"),
     "valu": (None, ""),
 }
 
