@@ -51,8 +51,8 @@ COUNTER_TRAFFIC = {
 # --workload ...), keyed by (workload, velocity engine): (bytes per launch,
 # SHA-256 of the sources, source list).
 OTHER_TRAFFIC = {
-    # k_time_hk<6,2>: FETCH 918.69 KiB x 2 + WRITE 40,702.84 KiB x 1
-    ("torus-k80-turbulent", "mfma"): (43_561_184, "310429af8df2502301e9988b4708f97f143cd342e07191f62799a99be583c96b", "hk"),
+    # k_time_hk<6,2>: FETCH 928.44 KiB x 2 + WRITE 40,702.97 KiB x 1
+    ("torus-k80-turbulent", "mfma"): (43_581_208, "3e37bca5bbe0fc4e4ce3fe2b01e78d55423a5e692ee4decdb9fead9bb65ce5d2", "hk"),
     # k_dirichlet_mx<4,0> (the map's first launch; the cooperative tail adds FETCH 567 KiB x 2 +
     # WRITE 1,205 KiB): FETCH 74.44 KiB x 2 + WRITE 184,737 KiB x 1
     ("disk-dirichlet", "mfma"): (189_323_131, "0530b6f39824c7aa0375c9caa73ffc08a9c498db35718de461ca32a2414e19b4", "mfma"),
