@@ -332,7 +332,7 @@ def bench_other(args):
     ctx = pm.Context(0)
     ctx.set_velocity_engine(args.engine)
     if args.dir_tail >= 0:
-        ctx.set_dirichlet_tail(args.dir_tail)
+        ctx.set_dirichlet_tail(args.dir_tail, args.dir_hand)
     name = args.workload
     cpu = None
     calibration_copy(torch, dev, args.copy_mib)
@@ -391,7 +391,7 @@ def bench_other(args):
         fl = alg_flops_per_particle_step(len(wl.modes), K, "disk")
         eng = engine_in_use(pm, args.engine, K, "disk")
         mx = eng == "mfma"
-        tail_on = mx and args.dir_tail != 0  # the library's default hands sparse waves to the tail
+        tail_on = mx and (args.dir_tail != 0 or args.dir_hand > 0)  # the default hands sparse waves to the tail
         kname = f"k_dirichlet_mx<{K}>" + (f" + k_dirichlet_tail<{K}>" if tail_on else "")
         rl = {"bound": "mfma" if mx else "alu", "peak": PEAK_FP16_DENSE_TFLOPS if mx else PEAK_FP32_TFLOPS,
               "unit": "TFLOP/s", "kernel": kname if mx else f"k_dirichlet<float,{K}>",
@@ -604,6 +604,9 @@ def main():
     ap.add_argument("--dir-tail", type=int, default=-1,
                     help="disk walk: live lanes below which waves hand their walkers to the cooperative tail "
                          "(0 = off, -1 = library default)")
+    ap.add_argument("--dir-hand", type=int, default=0,
+                    help="disk walk: step count at which walkers move to the cooperative tail (0 = off; "
+                         "used with --dir-tail >= 0)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 512-set batched map reported beside the main line")
     ap.add_argument("--copy-mib", type=int, default=0,

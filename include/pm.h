@@ -381,19 +381,28 @@ int pm_set_dirichlet_compaction(pm_ctx *ctx, int dump_below, int launches);
 
 /* Cooperative tail of the matrix-core disk walk (Algorithm 2 on the unit
  * disk, FP32, K <= 4, zero, constant or linear source; other paths ignore
- * it; default live_below 4).  Once no fresh particle is left, a wave whose live lanes drop below
- * live_below (after 1,024 iterations in its launch) saves its walkers to a
- * pool and ends; one more launch runs every saved walker to its exit, one
- * walker per wave: the 64 lanes share each step (lane 16 f + j forms column
- * j of velocity form f, a row-wise sum adds them; one Philox draw per lane
- * gives the normals of 128 steps), so a long walk advances several times
- * faster than alone in a wave of the matrix-core walk.  Same walk, random
- * numbers, exit rule and cap; the velocity is summed in another order than
+ * it).  Walkers leave the matrix-core walk for a pool in two ways: once no
+ * fresh particle is left, a wave whose live lanes drop below live_below
+ * (after 1,024 iterations in its launch) saves all its walkers and ends;
+ * and (hand_steps > 0) every walker that has taken hand_steps steps is
+ * saved as soon as it reaches them, its lane taking the next particle.  One
+ * more launch then runs every saved walker to its exit, one walker per
+ * wave: the 64 lanes share each step (lane 16 f + j forms column j of
+ * velocity form f, a row-wise sum adds them; one Philox draw per lane gives
+ * the normals of 128 steps), so a long walk advances several times faster
+ * than alone in a wave of the matrix-core walk.  Same walk, random numbers,
+ * update, exit rule and cap; the velocity is summed in another order than
  * the matrix-core contraction, so a continued path differs from an
- * uninterrupted one in rounding, within the same FP32 bounds.  live_below in
- * 0..64 (0: off); while on, the compaction setting does not apply to this
- * path.  PM_EINVAL outside that range. */
-int pm_set_dirichlet_tail(pm_ctx *ctx, int live_below);
+ * uninterrupted one in rounding, within the same FP32 bounds.  Hand-over by
+ * step count depends on each walker's own steps only, so results are
+ * bitwise reproducible from call to call; hand-over of sparse waves depends
+ * on which walkers share a wave when the queue runs dry, so results may
+ * differ between calls in the rounding of the continued paths.  Walkers
+ * beyond the pool's room (resident lanes of the launch) stay in the walk.
+ * live_below in 0..64, hand_steps >= 0 and even (0, 0: off; default 4, 0).
+ * While on, the compaction setting does not apply to this path.  PM_EINVAL
+ * outside those ranges. */
+int pm_set_dirichlet_tail(pm_ctx *ctx, int live_below, int64_t hand_steps);
 
 /* Walkers the last Dirichlet call on ctx handed to the cooperative tail
  * (0 when the tail did not run).  Synchronises the context's stream. */

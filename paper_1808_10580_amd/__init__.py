@@ -104,7 +104,7 @@ def _declare(L):
     L.pm_set_dirichlet_source.argtypes = [_vp, C.c_int]
     L.pm_set_dirichlet_blocks_per_cu.argtypes = [_vp, C.c_int]
     L.pm_set_dirichlet_compaction.argtypes = [_vp, C.c_int, C.c_int]
-    L.pm_set_dirichlet_tail.argtypes = [_vp, C.c_int]
+    L.pm_set_dirichlet_tail.argtypes = [_vp, C.c_int, _i64]
     L.pm_dirichlet_tail_walkers.argtypes = [_vp, C.POINTER(_i64)]
     L.pm_autotune_time.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _d, _d, _i64, _u64, C.c_int,
                                    C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(_d)]
@@ -213,8 +213,8 @@ class Context:
     def set_dirichlet_compaction(self, dump_below: int = 0, launches: int = 8):
         _check(_lib().pm_set_dirichlet_compaction(self.h, dump_below, launches), "pm_set_dirichlet_compaction")
 
-    def set_dirichlet_tail(self, live_below: int = 0):
-        _check(_lib().pm_set_dirichlet_tail(self.h, live_below), "pm_set_dirichlet_tail")
+    def set_dirichlet_tail(self, live_below: int = 0, hand_steps: int = 0):
+        _check(_lib().pm_set_dirichlet_tail(self.h, live_below, hand_steps), "pm_set_dirichlet_tail")
 
     def dirichlet_tail_walkers(self) -> int:
         n = _i64(0)

@@ -117,6 +117,7 @@ struct pm_ctx {
     int dir_dump = 0;              // Dirichlet compaction (off): save waves with fewer live lanes
     int dir_launches = 8;          // ... over this many follow-up launches
     int dir_tail = 4;              // cooperative disk tail: hand over waves with fewer live lanes
+    int64_t dir_hand = 0;          // ... and walkers at this step count (0: off)
     unsigned long long *tail_count = nullptr;  // walkers the last disk walk handed to the tail (device)
     void *pool = nullptr;          // compaction pools: counters, states, indices
     size_t pool_cap = 0;
@@ -740,7 +741,7 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     // The cooperative tail (matrix-core disk walk, sources without Gaussians)
     // takes the place of the follow-up launches: one launch runs the saved
     // walkers one per wave.
-    const bool tail = mx && fk <= 1 && c->dir_tail > 0;
+    const bool tail = mx && fk <= 1 && (c->dir_tail > 0 || c->dir_hand > 0);
     const int n_follow = tail ? 0 : (c->dir_dump > 0 ? c->dir_launches : 0);
     DirPool pools[2] = {};
     c->tail_count = nullptr;
@@ -756,10 +757,12 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
             pools[q].head = (unsigned long long *)base + 2 * q + 1;
             pools[q].st = (double *)(base + 4 * sizeof(unsigned long long) + q * st_bytes);
             pools[q].ij = (uint32_t *)(base + 4 * sizeof(unsigned long long) + 2 * st_bytes + q * ij_bytes);
+            pools[q].cap = cap;
         }
         if (launch_zero_u64((unsigned long long *)base, 4, c->stream) != hipSuccess) return PM_EDEVICE;
     }
     a.min_iters = 1024;
+    a.hand_steps = tail ? c->dir_hand : 0;
 
     if (launch_zero_u64(c->d_queue, 1, c->stream) != hipSuccess) return PM_EDEVICE;
     if (mx && launch_check_disk_range(obs, n_obs, c->d_flags, c->stream) != hipSuccess) return PM_EDEVICE;
@@ -781,6 +784,7 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
             a.mode = 1;
             a.pin = pools[0];
             a.dump_below = 0;
+            a.hand_steps = 0;
             if (launch_pool_reset(pools[0].head, pools[1].count, c->stream) != hipSuccess) return PM_EDEVICE;
             if (launch_dirichlet_tail(a, fixed_consts(dt, kappa, std::ldexp(1.0, MX_DISK_SHIFT)), coef64,
                                       row_stride(p->domain, p->K), p->K, fk, c->n_cu, c->stream) != hipSuccess)
@@ -1456,10 +1460,11 @@ int pm_set_dirichlet_compaction(pm_ctx *c, int dump_below, int launches)
     return PM_OK;
 }
 
-int pm_set_dirichlet_tail(pm_ctx *c, int live_below)
+int pm_set_dirichlet_tail(pm_ctx *c, int live_below, int64_t hand_steps)
 {
-    if (!c || c->closed || live_below < 0 || live_below > 64) return PM_EINVAL;
+    if (!c || c->closed || live_below < 0 || live_below > 64 || hand_steps < 0 || (hand_steps & 1)) return PM_EINVAL;
     c->dir_tail = live_below;
+    c->dir_hand = hand_steps;
     return PM_OK;
 }
 

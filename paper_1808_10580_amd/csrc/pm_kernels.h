@@ -80,10 +80,11 @@ struct PayArgs {
 // Walkers saved between the launches of a compacted Dirichlet walk.
 constexpr int DIR_POOL_WORDS = 6 + PM_MAX_SOURCES;  // x hi, x lo, y hi, y lo, int f, steps, source integrals
 struct DirPool {
-    unsigned long long *count;  // walkers stored
+    unsigned long long *count;  // walkers stored (a hand-over past cap is counted but not stored)
     unsigned long long *head;   // next walker to deal when the pool is the input
     double *st;                 // [cap][DIR_POOL_WORDS]
     uint32_t *ij;               // [cap][2] particle and observation index
+    int64_t cap;
 };
 
 template <typename T>
@@ -116,6 +117,10 @@ struct DirArgs {
     int mode;
     int dump_below;
     int min_iters;
+    // Hand-over at a fixed step count (> 0): a walker that has taken
+    // hand_steps steps is saved to pout (while it has room) and its lane takes
+    // the next particle; which walkers move depends on their own steps only.
+    int64_t hand_steps;
     DirPool pin, pout;
 };
 

@@ -792,7 +792,8 @@ __global__ __launch_bounds__(256) void k_dirichlet_tail(const DirArgs<float> a, 
     for (int i = 0; i < B; ++i) c[i] = act ? (float)coef[j * row_stride + 3 * i + f] : 0.f;
     const float nj = (float)((j + 1) >> 1), ph = (j & 1) ? 0.25f : 0.f;  // cos = sin shifted a quarter turn
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    const int64_t count = (int64_t)uniform64((int64_t)*a.pin.count);
+    int64_t count = (int64_t)uniform64((int64_t)*a.pin.count);
+    count = count < a.pin.cap ? count : a.pin.cap;  // hand-overs past a full pool were not stored
     for (;;) {
         unsigned long long tk = 0;
         if (lane == 0) tk = atomicAdd(a.pin.head, 1ull);

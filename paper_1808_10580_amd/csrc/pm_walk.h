@@ -117,9 +117,42 @@ __device__ __forceinline__ void dirichlet_walk(const DirArgs<T> &a, const StepCo
 
     // input: fresh particles (mode 0) or saved walkers (mode 1)
     unsigned long long *const qhead = a.mode ? a.pin.head : a.queue;
-    const int64_t limit = a.mode ? (int64_t)uniform64((int64_t)*a.pin.count) : a.total;
+    int64_t limit = a.total;
+    if (a.mode) {
+        limit = (int64_t)uniform64((int64_t)*a.pin.count);
+        limit = limit < a.pin.cap ? limit : a.pin.cap;  // hand-overs past a full pool were not stored
+    }
     int iters = 0;
+    auto save = [&](double *S, int64_t slot) {
+        x.save(S[0], S[1]);
+        y.save(S[2], S[3]);
+        S[4] = I;
+        S[5] = (double)n;
+        if constexpr (FK == 2) {
+#pragma unroll
+            for (int q = 0; q < PM_MAX_SOURCES; ++q) S[6 + q] = Is[q];
+        }
+        a.pout.ij[2 * slot] = pi;
+        a.pout.ij[2 * slot + 1] = pj;
+    };
     for (;;) {
+        if (a.hand_steps > 0) {  // step counts are even here
+            const bool give = has && n >= a.hand_steps;
+            const unsigned long long gm = __ballot(give);
+            if (gm) {
+                const int first = __ffsll((long long)gm) - 1;
+                unsigned long long base = 0;
+                if (lane == first) base = atomicAdd(a.pout.count, (unsigned long long)__popcll(gm));
+                base = __shfl(base, first);
+                if (give) {
+                    const int64_t slot = (int64_t)base + __popcll(gm & ((1ull << lane) - 1ull));
+                    if (slot < a.pout.cap) {  // else the pool is full: keep walking here
+                        save(a.pout.st + slot * DIR_POOL_WORDS, slot);
+                        has = false;
+                    }
+                }
+            }
+        }
         const bool need = !has && !done;
         const unsigned long long m = __ballot(need);
         if (m) {
@@ -173,19 +206,13 @@ __device__ __forceinline__ void dirichlet_walk(const DirArgs<T> &a, const StepCo
             base = __shfl(base, first);
             if (has) {
                 const int64_t slot = (int64_t)base + __popcll(hm & ((1ull << lane) - 1ull));
-                double *S = a.pout.st + slot * DIR_POOL_WORDS;
-                x.save(S[0], S[1]);
-                y.save(S[2], S[3]);
-                S[4] = I;
-                S[5] = (double)n;
-                if constexpr (FK == 2) {
-#pragma unroll
-                    for (int q = 0; q < PM_MAX_SOURCES; ++q) S[6 + q] = Is[q];
+                if (slot < a.pout.cap) {
+                    save(a.pout.st + slot * DIR_POOL_WORDS, slot);
+                    has = false;
                 }
-                a.pout.ij[2 * slot] = pi;
-                a.pout.ij[2 * slot + 1] = pj;
             }
-            break;
+            // a full pool leaves some walkers here: the wave walks on
+            if (__ballot(has) == 0) break;
         }
         ++iters;
         const U4 w = philox4x32_10((uint32_t)(n >> 1), pi, pj, 0u, k0, k1);

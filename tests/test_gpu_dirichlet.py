@@ -298,9 +298,9 @@ def test_compaction_is_bitwise_neutral(pm, ctx, engine_of, prec, engine, dump, l
 
 @pytest.fixture
 def tail_of(ctx):
-    """Set the cooperative-tail threshold for one test; the default is restored after."""
-    def use(live_below):
-        ctx.set_dirichlet_tail(live_below)
+    """Set the cooperative-tail thresholds for one test; the default is restored after."""
+    def use(live_below, hand_steps=0):
+        ctx.set_dirichlet_tail(live_below, hand_steps)
         return live_below
     yield use
     ctx.set_dirichlet_tail(TAIL_DEFAULT)
@@ -317,8 +317,8 @@ def _path_stats(P, ref):
     return 1 - same.mean(), np.quantile(err, 0.99), np.quantile(perr, 0.99)
 
 
-@pytest.mark.parametrize("live_below", [64, 8])
-def test_tail_paths_match_oracle(pm, ctx, orc, engine_of, tail_of, live_below):
+@pytest.mark.parametrize("live_below,hand", [(64, 0), (8, 0), (0, 2000)])
+def test_tail_paths_match_oracle(pm, ctx, orc, engine_of, tail_of, live_below, hand):
     """Walkers handed to the cooperative tail (one walker per wave, the lanes
     sharing each step) follow the oracle's paths as closely as the
     matrix-core walk does: a flow at 1% strength and walks of a few thousand
@@ -330,18 +330,18 @@ def test_tail_paths_match_oracle(pm, ctx, orc, engine_of, tail_of, live_below):
     engine_of("mfma")
     stats = {}
     ref = None
-    for lb in (0, live_below):
-        tail_of(lb)
+    for key, lb, hs in (("off", 0, 0), ("on", live_below, hand)):
+        tail_of(lb, hs)
         out, st, r = _run_both(pm, ctx, orc, "fp32", Np=1000, kappa=0.05, scale=0.01)
         ref = ref or r
         assert st == pm.PM_OK
         n_tail = ctx.dirichlet_tail_walkers()
-        stats[lb] = _path_stats(np_(out["paths"]), ref)
-        print("tail %d: %d walkers in the tail; different exit steps %.4f; exit point error p99 %.2e; "
-              "payoff error p99 %.2e" % ((lb, n_tail) + stats[lb]))
-        assert (n_tail > 0) == (lb > 0)
-    f0, e0, p0 = stats[0]
-    f1, e1, p1 = stats[live_below]
+        stats[key] = _path_stats(np_(out["paths"]), ref)
+        print("tail %s (%d, %d): %d walkers in the tail; different exit steps %.4f; exit point error p99 %.2e; "
+              "payoff error p99 %.2e" % ((key, lb, hs, n_tail) + stats[key]))
+        assert (n_tail > 0) == (key == "on")
+    f0, e0, p0 = stats["off"]
+    f1, e1, p1 = stats["on"]
     assert f1 <= f0 + 0.01
     assert e1 <= max(2 * e0, 1e-5)
     assert p1 <= max(2 * p0, 1e-5)
@@ -372,10 +372,33 @@ def test_tail_capped_walkers_and_sources(pm, ctx, orc, engine_of, tail_of):
     assert stats[64][2] <= max(2 * stats[0][2], 1e-5)
 
 
+def test_tail_hand_over_by_step_count_is_reproducible(pm, ctx, engine_of, tail_of):
+    """Hand-over at a fixed step count depends on each walker's own steps:
+    two calls give the same paths bit for bit, and a walker whose walk is
+    shorter than the hand-over count keeps the matrix-core walk's path."""
+    engine_of("mfma")
+    modes, u = _flow(0.01)
+    prob = pm.Problem(ctx, "disk", modes, prec="fp32")
+    runs = []
+    for lb, hs in ((0, 2000), (0, 2000), (0, 0)):
+        tail_of(lb, hs)
+        out = prob.observe_dirichlet(u, W.fld("const", [-1.0]), W.fld("cos_m_theta", [3]), OBS, 0.05, 1e-3, 1000,
+                                     31, 10**6, paths=True)
+        assert ctx.sync() == pm.PM_OK
+        runs.append((np_(out["paths"]).copy(), ctx.dirichlet_tail_walkers()))
+    (P1, n1), (P2, n2), (P0, n0) = runs
+    short = P0[..., 3] < 2000
+    print("hand-over at 2,000 steps: %d walkers in the tail; %d of %d walks shorter" % (n1, short.sum(), short.size))
+    assert n1 == n2 == np.sum(P0[..., 3] > 2000) and n1 > 0 and n0 == 0
+    assert np.array_equal(P1, P2)
+    assert np.array_equal(P1[short], P0[short])
+    prob.close()
+
+
 def test_tail_setting_range(pm, ctx):
-    for bad in (-1, 65):
+    for bad in ((-1, 0), (65, 0), (4, -2), (4, 3)):
         with pytest.raises(pm.PMError):
-            ctx.set_dirichlet_tail(bad)
+            ctx.set_dirichlet_tail(*bad)
     ctx.set_dirichlet_tail(TAIL_DEFAULT)
 
 
