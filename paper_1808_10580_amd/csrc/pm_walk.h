@@ -75,7 +75,10 @@ __device__ __forceinline__ void dirichlet_walk(const DirArgs<T> &a, const StepCo
                     }
                 }
             } else {
-                I += source_at<FK>(a.f, x.value(), y.value()) * a.dtd;  // left point
+                // left point; a constant source (p0 = p1 = 0, wave-uniform)
+                // adds p2 dt without the coordinates, bitwise the same value
+                if (FK == 0 && a.f.p[0] == 0.0 && a.f.p[1] == 0.0) I += a.f.p[2] * a.dtd;
+                else I += source_at<FK>(a.f, x.value(), y.value()) * a.dtd;
             }
             n += 1;
             // The exit test is decided in FP64.  FP32 particles first try the
