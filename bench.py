@@ -44,8 +44,8 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 COUNTER_TRAFFIC = {
     # k_time<float,6,3>: FETCH 157.25 KiB x 2 + WRITE 77,480.78 KiB x 1
     "valu": (79_662_368, "3b284018099e00ed8b8ca29fbfcbd81e7f33371ba6f8cff6f3ffc09d0a75e464"),
-    # k_time_mx<6>: FETCH 61.25 KiB x 2 + WRITE 79,140.34 KiB x 1
-    "mfma": (81_164_899, "0530b6f39824c7aa0375c9caa73ffc08a9c498db35718de461ca32a2414e19b4"),
+    # k_time_mx<6>: FETCH 61.19 KiB x 2 + WRITE 79,140.34 KiB x 1
+    "mfma": (81_164_771, "9062062afbe008a4c9da8a961256c5dcefea9898a2a45066f48068b99a67fdf5"),
 }
 # The same for the dominant kernel of the other workloads (bench.py
 # --workload ...), keyed by (workload, velocity engine): (bytes per launch,
@@ -53,9 +53,9 @@ COUNTER_TRAFFIC = {
 OTHER_TRAFFIC = {
     # k_time_hk<6,2>: FETCH 928.44 KiB x 2 + WRITE 40,702.97 KiB x 1
     ("torus-k80-turbulent", "mfma"): (43_581_208, "3e37bca5bbe0fc4e4ce3fe2b01e78d55423a5e692ee4decdb9fead9bb65ce5d2", "hk"),
-    # k_dirichlet_mx<4,0> (the map's first launch; the cooperative tail adds FETCH 567 KiB x 2 +
-    # WRITE 1,205 KiB): FETCH 74.44 KiB x 2 + WRITE 184,737 KiB x 1
-    ("disk-dirichlet", "mfma"): (189_323_131, "0530b6f39824c7aa0375c9caa73ffc08a9c498db35718de461ca32a2414e19b4", "mfma"),
+    # k_dirichlet_mx<4,0> (the map's first launch; the cooperative tail adds FETCH 552 KiB x 2 +
+    # WRITE 1,207 KiB): FETCH 83.06 KiB x 2 + WRITE 184,838.91 KiB x 1
+    ("disk-dirichlet", "mfma"): (189_445_145, "9062062afbe008a4c9da8a961256c5dcefea9898a2a45066f48068b99a67fdf5", "mfma"),
     # k_dirichlet<float,4,0,SC>: FETCH 90.13 KiB x 2 + WRITE 185,431.22 KiB x 1
     ("disk-dirichlet", "valu"): (190_066_144, "3b284018099e00ed8b8ca29fbfcbd81e7f33371ba6f8cff6f3ffc09d0a75e464", "valu"),
 }
@@ -85,7 +85,7 @@ COUNTERS = {
     "mfma": ({"valu_insts": 130.1, "valu_slots": 164.1, "fma_f32": 47.0, "mul_f32": 6.0, "add_f32": 4.0,
               "issue_frac": 1.03, "mfma_busy": 0.302,
               "source": "profiles/k_time_mx_torus-k6-fp32_pmc.md"},
-             "0530b6f39824c7aa0375c9caa73ffc08a9c498db35718de461ca32a2414e19b4"),
+             "9062062afbe008a4c9da8a961256c5dcefea9898a2a45066f48068b99a67fdf5"),
     "valu": (None, ""),
 }
 
