@@ -44,8 +44,8 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 COUNTER_TRAFFIC = {
     # k_time<float,6,3>: FETCH 157.25 KiB x 2 + WRITE 77,480.78 KiB x 1
     "valu": (79_662_368, "3b284018099e00ed8b8ca29fbfcbd81e7f33371ba6f8cff6f3ffc09d0a75e464"),
-    # k_time_mx<6>: FETCH 61.19 KiB x 2 + WRITE 79,140.34 KiB x 1
-    "mfma": (81_164_771, "9062062afbe008a4c9da8a961256c5dcefea9898a2a45066f48068b99a67fdf5"),
+    # k_time_mx<6>: FETCH 59.88 KiB x 2 + WRITE 40,846.84 KiB x 1
+    "mfma": (41_949_658, "9bc8e9a8bc86835d13f4f520a6805d9ba5d7694875b2f17b45dfb98ed6fbdf3f"),
 }
 # The same for the dominant kernel of the other workloads (bench.py
 # --workload ...), keyed by (workload, velocity engine): (bytes per launch,
@@ -53,9 +53,9 @@ COUNTER_TRAFFIC = {
 OTHER_TRAFFIC = {
     # k_time_hk<6,2>: FETCH 928.44 KiB x 2 + WRITE 40,702.97 KiB x 1
     ("torus-k80-turbulent", "mfma"): (43_581_208, "3e37bca5bbe0fc4e4ce3fe2b01e78d55423a5e692ee4decdb9fead9bb65ce5d2", "hk"),
-    # k_dirichlet_mx<4,0> (the map's first launch; the cooperative tail adds FETCH 552 KiB x 2 +
-    # WRITE 1,207 KiB): FETCH 83.06 KiB x 2 + WRITE 184,838.91 KiB x 1
-    ("disk-dirichlet", "mfma"): (189_445_145, "9062062afbe008a4c9da8a961256c5dcefea9898a2a45066f48068b99a67fdf5", "mfma"),
+    # k_dirichlet_mx<4,0> (the map's first launch; the cooperative tail adds FETCH 565 KiB x 2 +
+    # WRITE 1,205 KiB): FETCH 78.44 KiB x 2 + WRITE 184,847.69 KiB x 1
+    ("disk-dirichlet", "mfma"): (189_444_674, "9bc8e9a8bc86835d13f4f520a6805d9ba5d7694875b2f17b45dfb98ed6fbdf3f", "mfma"),
     # k_dirichlet<float,4,0,SC>: FETCH 90.13 KiB x 2 + WRITE 185,431.22 KiB x 1
     ("disk-dirichlet", "valu"): (190_066_144, "3b284018099e00ed8b8ca29fbfcbd81e7f33371ba6f8cff6f3ffc09d0a75e464", "valu"),
 }
@@ -83,9 +83,9 @@ PEAK_FP16_DENSE_TFLOPS = 2500.0
 # kernel's cycles per SIMD).
 COUNTERS = {
     "mfma": ({"valu_insts": 130.1, "valu_slots": 164.1, "fma_f32": 47.0, "mul_f32": 6.0, "add_f32": 4.0,
-              "issue_frac": 1.03, "mfma_busy": 0.302,
+              "issue_frac": 1.03, "mfma_busy": 0.301,
               "source": "profiles/k_time_mx_torus-k6-fp32_pmc.md"},
-             "9062062afbe008a4c9da8a961256c5dcefea9898a2a45066f48068b99a67fdf5"),
+             "9bc8e9a8bc86835d13f4f520a6805d9ba5d7694875b2f17b45dfb98ed6fbdf3f"),
     "valu": (None, ""),
 }
 

@@ -625,6 +625,10 @@ int observe_time_core(pm_ctx *c, const pm_problem *p, int n_u, const double *u, 
             ma.fx = fixed_consts(dte, kappa);
             ma.gauss = ma.fx.g2;
             ma.sets = mx_sets;
+            if (n_read == 1 && !rp) {  // single readout: 8-byte fixed-point final states
+                ma.fix_states = (uint32_t *)c->states;
+                pa.fix_states = ma.fix_states;
+            }
             ma.vmax_fast = (float)((0.45 - 5.9 * std::sqrt(2.0 * kappa * dte)) / dte -
                                    std::max(std::fabs(p->v0[0]), std::fabs(p->v0[1])));
             le = launch_time_mx(ma, p->K, c->n_cu, c->bpc ? c->bpc : c->tune_bpc_mx[p->K], c->stream);

@@ -65,6 +65,9 @@ struct TimeArgs {
 
 struct PayArgs {
     const double *states;  // [n_read][n_chunks][64][2]
+    // fixed-point final states of the small-K matrix-core kernel, [n_chunks][64]
+    // (X, Y) as 32-bit fractions of the period; when set, states is unused
+    const uint32_t *fix_states;
     int64_t n_chunks;      // per readout
     int n_read;
     int n_u;

@@ -324,8 +324,17 @@ __global__ __launch_bounds__(256) void k_time_payoff(const PayArgs a)
     const int64_t j = c / cpo, q = c - j * cpo;
     const int64_t i = q * 64 + lane;
     const bool act = i < np;
-    const double *S = a.states + 2 * (ga * 64 + lane);
-    const double xd = S[0] - floor(S[0]), yd = S[1] - floor(S[1]);
+    double sx, sy;
+    if (a.fix_states) {  // position = X 2^-32 in [-1/2, 1/2)
+        const uint2 F = reinterpret_cast<const uint2 *>(a.fix_states)[ga * 64 + lane];
+        sx = (double)(int32_t)F.x * 0x1p-32;
+        sy = (double)(int32_t)F.y * 0x1p-32;
+    } else {
+        const double *S = a.states + 2 * (ga * 64 + lane);
+        sx = S[0];
+        sy = S[1];
+    }
+    const double xd = sx - floor(sx), yd = sy - floor(sy);
     double e = 0.0;
     if (act) e = field_eval(a.theta0, xd, yd);
     if (a.endpoints && act) {

@@ -127,6 +127,9 @@ struct MxTimeArgs {
     // uniform, so that the normals come out times sqrt(2 kappa dt) 2^32
     float gauss;
     const unsigned char *sets;   // [n_u][MX_SET_BYTES]
+    // single readout: the final states as fixed-point pairs (X, Y), 8 bytes
+    // per particle at [chunk][64], for the payoff kernel (t.states unused)
+    uint32_t *fix_states;
     // A parameter set whose vbound is at most vmax_fast moves a particle by
     // less than 0.45 of the period per step (drift plus the largest normal),
     // so the 32-bit increment of the fixed-point update cannot overflow;

@@ -679,9 +679,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         if (wide) walk(std::true_type{});
         else walk(std::false_type{});
         if (!MT) {
-            double *S = a.states + 2 * ((cb + ch) * 64 + lane);
-            S[0] = x.value();
-            S[1] = y.value();
+            if (m.fix_states) {  // 8 bytes per particle: the fixed-point pair itself
+                reinterpret_cast<uint2 *>(m.fix_states)[(cb + ch) * 64 + lane] = make_uint2(x.X, y.X);
+            } else {
+                double *S = a.states + 2 * ((cb + ch) * 64 + lane);
+                S[0] = x.value();
+                S[1] = y.value();
+            }
         }
     }
 }
