@@ -42,22 +42,22 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 # reported when the sources still hash to the recorded value, else null.
 # Per velocity engine: (bytes per launch, SHA-256 of the kernel's sources).
 COUNTER_TRAFFIC = {
-    # k_time<float,6,3>: FETCH 157.25 KiB x 2 + WRITE 77,480.78 KiB x 1
-    "valu": (79_662_368, "3b284018099e00ed8b8ca29fbfcbd81e7f33371ba6f8cff6f3ffc09d0a75e464"),
-    # k_time_mx<6>: FETCH 59.88 KiB x 2 + WRITE 40,846.84 KiB x 1
-    "mfma": (41_949_658, "9bc8e9a8bc86835d13f4f520a6805d9ba5d7694875b2f17b45dfb98ed6fbdf3f"),
+    # k_time<float,6,3>: FETCH 162.25 KiB x 2 + WRITE 77,480.78 KiB x 1
+    "valu": (79_672_607, "2dd9df4c53f1e6257a148b10f43ef080506abd850923374e7b7c964530b16eb4"),
+    # k_time_mx<6>: FETCH 60.00 KiB x 2 + WRITE 40,846.84 KiB x 1
+    "mfma": (41_950_044, "0dc20df2500c47a51e0fc5aaa4dbf168b9fd23536247385c9e35f1b53c495e6e"),
 }
 # The same for the dominant kernel of the other workloads (bench.py
 # --workload ...), keyed by (workload, velocity engine): (bytes per launch,
 # SHA-256 of the sources, source list).
 OTHER_TRAFFIC = {
-    # k_time_hk<6,2>: FETCH 928.44 KiB x 2 + WRITE 40,702.97 KiB x 1
-    ("torus-k80-turbulent", "mfma"): (43_581_208, "3e37bca5bbe0fc4e4ce3fe2b01e78d55423a5e692ee4decdb9fead9bb65ce5d2", "hk"),
-    # k_dirichlet_mx<4,0> (the map's first launch; the cooperative tail adds FETCH 565 KiB x 2 +
-    # WRITE 1,205 KiB): FETCH 78.44 KiB x 2 + WRITE 184,847.69 KiB x 1
-    ("disk-dirichlet", "mfma"): (189_444_674, "9bc8e9a8bc86835d13f4f520a6805d9ba5d7694875b2f17b45dfb98ed6fbdf3f", "mfma"),
-    # k_dirichlet<float,4,0,SC>: FETCH 90.13 KiB x 2 + WRITE 185,431.22 KiB x 1
-    ("disk-dirichlet", "valu"): (190_066_144, "3b284018099e00ed8b8ca29fbfcbd81e7f33371ba6f8cff6f3ffc09d0a75e464", "valu"),
+    # k_time_hk<6,2>: FETCH 928.31 KiB x 2 + WRITE 40,702.97 KiB x 1
+    ("torus-k80-turbulent", "mfma"): (43_581_020, "943bd334f9cbaee4f83cc9298f2a5b494511165953a5db3478281d899ee0150b", "hk"),
+    # k_dirichlet_mx<4,0> (the map's first launch; the cooperative tail adds FETCH 557 KiB x 2 +
+    # WRITE 1,206 KiB): FETCH 77.00 KiB x 2 + WRITE 184,815.88 KiB x 1
+    ("disk-dirichlet", "mfma"): (189_409_157, "0dc20df2500c47a51e0fc5aaa4dbf168b9fd23536247385c9e35f1b53c495e6e", "mfma"),
+    # k_dirichlet<float,4,0,SC>: FETCH 152.88 KiB x 2 + WRITE 185,066.12 KiB x 1
+    ("disk-dirichlet", "valu"): (189_820_805, "2dd9df4c53f1e6257a148b10f43ef080506abd850923374e7b7c964530b16eb4", "valu"),
 }
 KERNEL_SOURCES = {
     "hk": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
@@ -85,7 +85,7 @@ COUNTERS = {
     "mfma": ({"valu_insts": 130.1, "valu_slots": 164.1, "fma_f32": 47.0, "mul_f32": 6.0, "add_f32": 4.0,
               "issue_frac": 1.03, "mfma_busy": 0.301,
               "source": "profiles/k_time_mx_torus-k6-fp32_pmc.md"},
-             "9bc8e9a8bc86835d13f4f520a6805d9ba5d7694875b2f17b45dfb98ed6fbdf3f"),
+             "0dc20df2500c47a51e0fc5aaa4dbf168b9fd23536247385c9e35f1b53c495e6e"),
     "valu": (None, ""),
 }
 

@@ -496,25 +496,32 @@ struct FixCoord {
 // FP64 value.
 struct DiskFix {
     int32_t X;
+    float h;  // (float)X 2^-30, kept beside X: the exit test of one step and the bases of the next share it
     static __device__ __forceinline__ void normals(uint32_t wa, uint32_t wb, const StepConsts<float> &c, float &z0,
                                                    float &z1)
     {
         box_muller_r2(wa, wb, c.g2, 0.f, 0.f, z0, z1);
     }
-    __device__ __forceinline__ void set(double x) { X = (int32_t)llrint(x * 0x1p30); }
-    __device__ __forceinline__ float at() const { return (float)X * 0x1p-30f; }
+    __device__ __forceinline__ void sync() { h = (float)X * 0x1p-30f; }
+    __device__ __forceinline__ void set(double x)
+    {
+        X = (int32_t)llrint(x * 0x1p30);
+        sync();
+    }
+    __device__ __forceinline__ float at() const { return h; }
     __device__ __forceinline__ double value() const { return (double)X * 0x1p-30; }
     __device__ __forceinline__ void advance(float vel, float zs, const StepConsts<float> &c)
     {
         const float d = __builtin_fmaf(-c.dth, vel, zs);
         X += (int32_t)__builtin_fminf(__builtin_fmaxf(d, -0x1p29f), 0x1p29f);
+        sync();
     }
     __device__ __forceinline__ void save(double &a, double &b) const
     {
         a = value();
         b = 0.0;
     }
-    __device__ __forceinline__ void load(double a, double) { X = (int32_t)llrint(a * 0x1p30); }
+    __device__ __forceinline__ void load(double a, double) { set(a); }
 };
 
 // LDS writes of one wave visible to the same wave's later reads.
@@ -761,8 +768,7 @@ __global__ __launch_bounds__(256) void k_dirichlet_mx(const DirArgs<float> a, co
 // draws the normals of Philox block b0 + l, so one draw serves 128 steps;
 // each step reads its pair with a wave-uniform lane index.  Normals,
 // update, exit test, source integral and cap are those of dirichlet_walk with
-// DiskFix, every lane holding the walker's state; lane 0 writes the exit
-// record.
+// DiskFix, every lane holding the walker's state and writing its exit record.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float row_shr_add(float v, int n)
 {
@@ -811,69 +817,79 @@ __global__ __launch_bounds__(256) void k_dirichlet_tail(const DirArgs<float> a, 
         int64_t n = (int64_t)S[5];
         const uint32_t pi = a.pin.ij[2 * w_ix], pj = a.pin.ij[2 * w_ix + 1];
         const int64_t t = (int64_t)pj * a.np + pi;
+        // One Philox draw per lane gives the normals of the next 128 steps
+        // (blocks b0 .. b0 + 63); the step loop's only branch is its latch.
         double xd = x.value(), yd = y.value();
-        float zr[4] = {0.f, 0.f, 0.f, 0.f};
-        int64_t b0 = INT64_MIN / 2;  // no block drawn yet
-        for (;;) {
-            const int64_t blk = n >> 1;
-            if (blk - b0 >= 64) {  // normals of blocks blk .. blk + 63, one per lane, in units
-                b0 = blk;
+        bool out = false;
+        do {
+            const int64_t b0 = n >> 1;
+            float zr[4];
+            {
                 const U4 w = philox4x32_10((uint32_t)(b0 + lane), pi, pj, 0u, k0, k1);
                 DiskFix::normals(w.x, w.y, fx, zr[0], zr[1]);
                 DiskFix::normals(w.z, w.w, fx, zr[2], zr[3]);
             }
-            const int src = (int)(blk - b0);
-            const bool second = (n & 1) != 0;
-            const float z0 = read_lane(second ? zr[2] : zr[0], src);
-            const float z1 = read_lane(second ? zr[3] : zr[1], src);
+            int s = (int)(n - 2 * b0);
+            const int64_t left = a.max_steps - n;  // steps to the cap
+            const int lim = left < 128 - s ? s + (int)left : 128;
+            do {
+                const int src = s >> 1;
+                const bool second = (s & 1) != 0;
+                const float z0 = read_lane(second ? zr[2] : zr[0], src);
+                const float z1 = read_lane(second ? zr[3] : zr[1], src);
 
-            const float xs = x.at(), ys = y.at();
-            float px[B];
-            trig_basis<float, K>(xs, px);
-            float tj = c[0];
+                const float xs = x.at(), ys = y.at();
+                float px[B];
+                trig_basis<float, K>(xs, px);
+                // cosine and sine entries in two sums: half the dependent chain
+                float tc = c[0], ts = 0.f;
 #pragma unroll
-            for (int i = 1; i < B; ++i) tj = __builtin_fmaf(c[i], px[i], tj);
-            const float pyj = j == 0 ? 1.f : __builtin_amdgcn_sinf(__builtin_fmaf(nj, ys, ph));
-            float v = act ? tj * pyj : 0.f;
-            v = row_shr_add(v, 1);
-            v = row_shr_add(v, 2);
-            v = row_shr_add(v, 4);
-            v = row_shr_add(v, 8);
-            const float F0 = read_lane(v, 15), FX = read_lane(v, 31), FY = read_lane(v, 47);
-            const float wgt = 1.f - (xs * xs + ys * ys);
-            const float chi = wgt * wgt;
-            const float g4 = 4.f * wgt * F0;
-            const float vx = __builtin_fmaf(chi, FX, -(g4 * ys));
-            const float vy = __builtin_fmaf(chi, FY, g4 * xs);
+                for (int i = 1; i < B; i += 2) {
+                    tc = __builtin_fmaf(c[i], px[i], tc);
+                    ts = __builtin_fmaf(c[i + 1], px[i + 1], ts);
+                }
+                const float tj = tc + ts;
+                const float pyj = j == 0 ? 1.f : __builtin_amdgcn_sinf(__builtin_fmaf(nj, ys, ph));
+                float v = act ? tj * pyj : 0.f;
+                v = row_shr_add(v, 1);
+                v = row_shr_add(v, 2);
+                v = row_shr_add(v, 4);
+                v = row_shr_add(v, 8);
+                const float F0 = read_lane(v, 15), FX = read_lane(v, 31), FY = read_lane(v, 47);
+                const float wgt = 1.f - (xs * xs + ys * ys);
+                const float chi = wgt * wgt;
+                const float g4 = 4.f * wgt * F0;
+                const float vx = __builtin_fmaf(chi, FX, -(g4 * ys));
+                const float vy = __builtin_fmaf(chi, FY, g4 * xs);
 
-            DiskFix nx = x, ny = y;  // the walk's update
-            nx.advance(vx + a.v0x, z0, fx);
-            ny.advance(vy + a.v0y, z1, fx);
-            I += source_at<FK>(a.f, xd, yd) * a.dtd;  // left point
-            n += 1;
-            const double nxd = nx.value(), nyd = ny.value();
-            const bool out = nxd * nxd + nyd * nyd >= 1.0;
-            if (out || n >= a.max_steps) {
-                double ex = nxd, ey = nyd;
-                if (out) {  // radial projection onto the circle
-                    const double r = sqrt(nxd * nxd + nyd * nyd);
-                    ex = nxd / r;
-                    ey = nyd / r;
-                }
-                if (lane == 0) {
-                    a.exitp[2 * t] = ex;
-                    a.exitp[2 * t + 1] = ey;
-                    a.integ[t] = I;
-                    a.nsteps[t] = (double)n;
-                    a.capped[t] = out ? 0 : 1;
-                }
-                break;
-            }
-            x = nx;
-            y = ny;
-            xd = nxd;
-            yd = nyd;
+                x.advance(vx + a.v0x, z0, fx);  // the walk's update
+                y.advance(vy + a.v0y, z1, fx);
+                I += source_at<FK>(a.f, xd, yd) * a.dtd;  // left point
+                n += 1;
+                xd = x.value();
+                yd = y.value();
+                // |x|^2 >= 1 tested on the unscaled integers (the 2^-30 scaling
+                // is exact, so the rounding and the outcome are the same); the
+                // same in every lane, so the branch is uniform
+                const double Xd = (double)x.X, Yd = (double)y.X;
+                out = __ballot(Xd * Xd + Yd * Yd >= 0x1p60) != 0;
+                ++s;
+            } while (!out & (s < lim));
+        } while (!out && n < a.max_steps);
+        double ex = xd, ey = yd;
+        if (out) {  // radial projection onto the circle
+            const double r = sqrt(xd * xd + yd * yd);
+            ex = xd / r;
+            ey = yd / r;
         }
+        // every lane writes the same record: no lane-0 branch at the end of the
+        // loop, which the compiler could merge with the next walker's lane-0
+        // fetch and so split the wave around the shuffle
+        a.exitp[2 * t] = ex;
+        a.exitp[2 * t + 1] = ey;
+        a.integ[t] = I;
+        a.nsteps[t] = (double)n;
+        a.capped[t] = out ? 0 : 1;
     }
 }
 
