@@ -53,9 +53,9 @@ COUNTER_TRAFFIC = {
 OTHER_TRAFFIC = {
     # k_time_hk<6,2>: FETCH 928.31 KiB x 2 + WRITE 40,702.97 KiB x 1
     ("torus-k80-turbulent", "mfma"): (43_581_020, "943bd334f9cbaee4f83cc9298f2a5b494511165953a5db3478281d899ee0150b", "hk"),
-    # k_dirichlet_mx<4,0> (the map's first launch; the cooperative tail adds FETCH 557 KiB x 2 +
-    # WRITE 1,206 KiB): FETCH 77.00 KiB x 2 + WRITE 184,815.88 KiB x 1
-    ("disk-dirichlet", "mfma"): (189_409_157, "0dc20df2500c47a51e0fc5aaa4dbf168b9fd23536247385c9e35f1b53c495e6e", "mfma"),
+    # k_dirichlet_mx<4,0> (the map's first launch; the cooperative tail adds FETCH 1,360 KiB x 2 +
+    # WRITE 2,442 KiB): FETCH 77.50 KiB x 2 + WRITE 184,147.31 KiB x 1
+    ("disk-dirichlet", "mfma"): (188_725_568, "e0a0ef179be3d9b21bb6a6ae67a3ec48bcab077e59a05fa59e530da02693cd6d", "mfma_disk"),
     # k_dirichlet<float,4,0,SC>: FETCH 152.88 KiB x 2 + WRITE 185,066.12 KiB x 1
     ("disk-dirichlet", "valu"): (189_820_805, "2dd9df4c53f1e6257a148b10f43ef080506abd850923374e7b7c964530b16eb4", "valu"),
 }
@@ -67,6 +67,12 @@ KERNEL_SOURCES = {
     "mfma": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
              "paper_1808_10580_amd/csrc/pm_walk.h", "paper_1808_10580_amd/csrc/pm_mx.h",
              "paper_1808_10580_amd/csrc/pm_split.h", "paper_1808_10580_amd/csrc/pm_mx.hip"),
+    # the disk walk's traffic also depends on the host side's launch settings
+    # (the tail's hand-over threshold, blocks per compute unit)
+    "mfma_disk": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
+                  "paper_1808_10580_amd/csrc/pm_walk.h", "paper_1808_10580_amd/csrc/pm_mx.h",
+                  "paper_1808_10580_amd/csrc/pm_split.h", "paper_1808_10580_amd/csrc/pm_mx.hip",
+                  "paper_1808_10580_amd/csrc/pm_abi.hip"),
 }
 # Matrix-core FLOPs issued per particle-step by the small-K engine: per 64
 # particles two 32-column blocks x three v_mfma_f32_32x32x16_f16 (32 x 32 x 16

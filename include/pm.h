@@ -399,7 +399,7 @@ int pm_set_dirichlet_compaction(pm_ctx *ctx, int dump_below, int launches);
  * on which walkers share a wave when the queue runs dry, so results may
  * differ between calls in the rounding of the continued paths.  Walkers
  * beyond the pool's room (resident lanes of the launch) stay in the walk.
- * live_below in 0..64, hand_steps >= 0 and even (0, 0: off; default 4, 0).
+ * live_below in 0..64, hand_steps >= 0 and even (0, 0: off; default 8, 0).
  * While on, the compaction setting does not apply to this path.  PM_EINVAL
  * outside those ranges. */
 int pm_set_dirichlet_tail(pm_ctx *ctx, int live_below, int64_t hand_steps);

@@ -116,7 +116,7 @@ struct pm_ctx {
     int dir_bpc = 2;               // Dirichlet persistent blocks per CU (0 = occupancy)
     int dir_dump = 0;              // Dirichlet compaction (off): save waves with fewer live lanes
     int dir_launches = 8;          // ... over this many follow-up launches
-    int dir_tail = 4;              // cooperative disk tail: hand over waves with fewer live lanes
+    int dir_tail = 8;              // cooperative disk tail: hand over waves with fewer live lanes
     int64_t dir_hand = 0;          // ... and walkers at this step count (0: off)
     unsigned long long *tail_count = nullptr;  // walkers the last disk walk handed to the tail (device)
     void *pool = nullptr;          // compaction pools: counters, states, indices

@@ -307,7 +307,7 @@ def tail_of(ctx):
 
 
 # the library's default threshold of the cooperative disk tail
-TAIL_DEFAULT = 4
+TAIL_DEFAULT = 8
 
 
 def _path_stats(P, ref):
