@@ -13,6 +13,7 @@ later vector instruction has read (which makes the hardware wait for it)
 within the following 64 vector instructions (at 4 or more cycles each, past
 the longest MFMA latency).
 """
+import functools
 import os
 import re
 import shutil
@@ -71,6 +72,11 @@ def hazards(asm_text):
     return found
 
 
+@functools.lru_cache(maxsize=None)
+def _compile_cached(src, extra):
+    return _compile(src, list(extra))
+
+
 def _compile(src, extra):
     import build  # the library's own compile flags
 
@@ -103,7 +109,55 @@ def test_checker_flags_a_planted_hazard():
 def test_no_inline_asm_inside_an_mfma_in_flight(src):
     import build
 
-    text = _compile(src, build.EXTRA.get(src, []))
+    text = _compile_cached(src, tuple(build.EXTRA.get(src, [])))
     assert "v_mfma" in text and ";;#ASMSTART" in text
     bad = hazards(text)
     assert bad == [], bad[:5]
+
+
+# ---------------------------------------------------------------------------
+# The cooperative disk tail runs one walker per wave: lane 0 takes the next
+# walker index from the pool and a shuffle gives it to the other lanes, and
+# every loop of the kernel is left by the whole wave together (the walker's
+# state, and so each exit condition, is the same in every lane).  A loop that
+# the compiler lets lanes leave one by one is closed by an exec-mask update
+# `s_andn2_b64 exec, exec, ...`; once, a lane-0 branch that ended the walker
+# loop was merged with the next walker's lane-0 fetch in that way, so lanes
+# 1-63 re-entered the shuffle without lane 0 and walked a stale walker.
+# ---------------------------------------------------------------------------
+def functions(asm_text):
+    """(name, body) of each function in a device assembly listing."""
+    out = []
+    for body in re.split(r"\n(?=_Z\w+:)", asm_text):
+        name = body.split(":", 1)[0].strip()
+        if name.startswith("_Z"):
+            out.append((name, body.split(".Lfunc_end", 1)[0]))
+    return out
+
+
+def lane_by_lane_loop_exits(body):
+    return [l.strip() for l in body.split("\n") if l.strip().startswith("s_andn2_b64 exec, exec")]
+
+
+def test_loop_exit_check_flags_a_lane_by_lane_exit():
+    text = "\n".join([
+        "_Zkernel:",
+        ".LBB0_1:",
+        "\ts_or_b64 s[48:49], s[80:81], s[48:49]",
+        "\ts_andn2_b64 exec, exec, s[48:49]",
+        "\ts_cbranch_execnz .LBB0_1",
+        ".Lfunc_end0:",
+    ])
+    (name, body), = functions(text)
+    assert name == "_Zkernel" and len(lane_by_lane_loop_exits(body)) == 1
+    assert lane_by_lane_loop_exits(body.replace("s_andn2_b64 exec, exec", "s_andn2_b64 vcc, exec")) == []
+
+
+def test_disk_tail_loops_are_left_by_the_whole_wave():
+    import build
+
+    text = _compile_cached("pm_mx.hip", tuple(build.EXTRA.get("pm_mx.hip", [])))
+    tails = [(n, b) for n, b in functions(text) if "k_dirichlet_tail" in n]
+    assert len(tails) == 8  # K = 1..4, zero/constant/linear and general sources
+    for name, body in tails:
+        assert lane_by_lane_loop_exits(body) == [], name
