@@ -42,22 +42,22 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 FLOP
 # reported when the sources still hash to the recorded value, else null.
 # Per velocity engine: (bytes per launch, SHA-256 of the kernel's sources).
 COUNTER_TRAFFIC = {
-    # k_time<float,6,3>: FETCH 162.25 KiB x 2 + WRITE 77,480.78 KiB x 1
-    "valu": (79_672_607, "2dd9df4c53f1e6257a148b10f43ef080506abd850923374e7b7c964530b16eb4"),
-    # k_time_mx<6>: FETCH 60.00 KiB x 2 + WRITE 40,846.84 KiB x 1
-    "mfma": (41_950_044, "0dc20df2500c47a51e0fc5aaa4dbf168b9fd23536247385c9e35f1b53c495e6e"),
+    # k_time<float,6,3>: FETCH 161.81 KiB x 2 + WRITE 77,480.78 KiB x 1
+    "valu": (79_671_711, "900da7bf51e4b4156b12bf2f83a11f1379e33170f399d1018a0315eba7620f49"),
+    # k_time_mx<6>: FETCH 60.69 KiB x 2 + WRITE 40,846.84 KiB x 1
+    "mfma": (41_951_457, "def84aa17d9394b534620b9ddc860714a7a4d32c75dac12019d9daa3a412b344"),
 }
 # The same for the dominant kernel of the other workloads (bench.py
 # --workload ...), keyed by (workload, velocity engine): (bytes per launch,
 # SHA-256 of the sources, source list).
 OTHER_TRAFFIC = {
     # k_time_hk<6,2>: FETCH 928.31 KiB x 2 + WRITE 40,702.97 KiB x 1
-    ("torus-k80-turbulent", "mfma"): (43_581_020, "943bd334f9cbaee4f83cc9298f2a5b494511165953a5db3478281d899ee0150b", "hk"),
-    # k_dirichlet_mx<4,0> (the map's first launch; the cooperative tail adds FETCH 1,360 KiB x 2 +
-    # WRITE 2,442 KiB): FETCH 77.50 KiB x 2 + WRITE 184,147.31 KiB x 1
-    ("disk-dirichlet", "mfma"): (188_725_568, "e0a0ef179be3d9b21bb6a6ae67a3ec48bcab077e59a05fa59e530da02693cd6d", "mfma_disk"),
-    # k_dirichlet<float,4,0,SC>: FETCH 152.88 KiB x 2 + WRITE 185,066.12 KiB x 1
-    ("disk-dirichlet", "valu"): (189_820_805, "2dd9df4c53f1e6257a148b10f43ef080506abd850923374e7b7c964530b16eb4", "valu"),
+    ("torus-k80-turbulent", "mfma"): (43_581_023, "6912bad040a8595f18a03950f3a6507e174bee024c5640f766a4fd3b522fee09", "hk"),
+    # k_dirichlet_mx<4,0> (the map's first launch; the cooperative tail adds FETCH 1,346 KiB x 2 +
+    # WRITE 1,152 KiB): FETCH 71.38 KiB x 2 + WRITE 80,384.97 KiB x 1
+    ("disk-dirichlet", "mfma"): (82_460_384, "1139ace9298341cf2fb91a61b92203356194799916f171e6fb5854069a02bcfd", "mfma_disk"),
+    # k_dirichlet<float,4,0,SC>: FETCH 137.94 KiB x 2 + WRITE 80,194.91 KiB x 1
+    ("disk-dirichlet", "valu"): (82_402_081, "900da7bf51e4b4156b12bf2f83a11f1379e33170f399d1018a0315eba7620f49", "valu"),
 }
 KERNEL_SOURCES = {
     "hk": ("paper_1808_10580_amd/csrc/pm_device.h", "paper_1808_10580_amd/csrc/pm_kernels.h",
@@ -91,7 +91,7 @@ COUNTERS = {
     "mfma": ({"valu_insts": 130.1, "valu_slots": 164.1, "fma_f32": 47.0, "mul_f32": 6.0, "add_f32": 4.0,
               "issue_frac": 1.03, "mfma_busy": 0.301,
               "source": "profiles/k_time_mx_torus-k6-fp32_pmc.md"},
-             "0dc20df2500c47a51e0fc5aaa4dbf168b9fd23536247385c9e35f1b53c495e6e"),
+             "def84aa17d9394b534620b9ddc860714a7a4d32c75dac12019d9daa3a412b344"),
     "valu": (None, ""),
 }
 

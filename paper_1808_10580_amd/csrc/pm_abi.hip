@@ -682,9 +682,7 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     const int64_t total = np * n_obs;
     if ((st = ensure(c, &c->pay, &c->pay_cap, total * sizeof(double)))) return st;
     if ((st = ensure(c, &c->tau, &c->tau_cap, total * sizeof(double)))) return st;
-    if ((st = ensure(c, &c->integ, &c->integ_cap, total * sizeof(double)))) return st;
-    if ((st = ensure(c, &c->nsteps, &c->nsteps_cap, total * sizeof(double)))) return st;
-    if ((st = ensure(c, &c->exitp, &c->exitp_cap, 2 * total * sizeof(double)))) return st;
+    if ((st = ensure(c, &c->exitp, &c->exitp_cap, 4 * total * sizeof(double)))) return st;  // exit records
     if ((st = ensure(c, &c->capped, &c->capped_cap, total))) return st;
     const int64_t cpo = (np + 63) / 64;
     if ((st = ensure(c, &c->part, &c->part_cap, cpo * n_obs * 3 * sizeof(double)))) return st;
@@ -730,10 +728,7 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     a.v0x = (T)p->v0[0];
     a.v0y = (T)p->v0[1];
     a.f = fk == 0 ? fpoly : f;
-    a.exitp = (double *)c->exitp;
-    a.integ = (double *)c->integ;
-    a.nsteps = (double *)c->nsteps;
-    a.capped = (unsigned char *)c->capped;
+    a.rec = (double *)c->exitp;
     a.queue = c->d_queue;
     a.n_src = n_src;
     for (int q = 0; q < n_src; ++q)
@@ -812,11 +807,9 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     pa.total = total;
     pa.dtd = dt;
     pa.g = g;
-    pa.exitp = a.exitp;
-    pa.integ = a.integ;
-    pa.nsteps = a.nsteps;
+    pa.rec = a.rec;
     pa.tau = (double *)c->tau;
-    pa.capped = a.capped;
+    pa.capped = (unsigned char *)c->capped;
     pa.pay = (double *)c->pay;
     pa.paths = paths;
     pa.flags = c->d_flags;
@@ -835,7 +828,7 @@ int observe_dirichlet_impl(pm_ctx *c, const pm_problem *p, const double *u, cons
     fa.mean = tau_mean;
     fa.var = tau_var;
     if (launch_finalize(fa, n_obs, c->stream) != hipSuccess) return PM_EDEVICE;
-    if (launch_count_capped(a.capped, np, n_obs, n_capped, c->stream) != hipSuccess) return PM_EDEVICE;
+    if (launch_count_capped(pa.capped, np, n_obs, n_capped, c->stream) != hipSuccess) return PM_EDEVICE;
     for (int q = 0; q < n_src; ++q) {  // mean of each source integral per observation
         const double *vals = (const double *)c->integ_src + (size_t)q * total;
         if (launch_chunk_reduce(vals, np, n_obs, (double *)c->part3, c->d_flags, c->stream)) return PM_EDEVICE;

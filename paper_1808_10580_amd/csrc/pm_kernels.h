@@ -103,10 +103,10 @@ struct DirArgs {
     T v0x, v0y;
     double dtd;
     FieldArg f;
-    double *exitp;  // [total][2]
-    double *integ;   // [total] int_0^tau f dt
-    double *nsteps;  // [total] steps taken (an exact integer)
-    unsigned char *capped;
+    // [total][4], one 32-byte record per walker written once at its end: exit
+    // point x, y, int_0^tau f dt, steps taken n (n for an exit, -n - 1 for a
+    // capped path; exact integers)
+    double *rec;
     unsigned long long *queue;
     const int *order;  // device [n_obs]: queue position -> observation (longest walks first)
     // Gaussian sources (FK = 2): per particle int_0^tau exp(-w_s |X - c_s|^2) dt
@@ -127,14 +127,24 @@ struct DirArgs {
     DirPool pin, pout;
 };
 
+// One walker's exit record as a single 32-byte store (DirArgs::rec).
+__device__ __forceinline__ void write_exit_record(double *rec, int64_t t, double ex, double ey, double integ,
+                                                  int64_t n, bool exited)
+{
+    double4 r;
+    r.x = ex;
+    r.y = ey;
+    r.z = integ;
+    r.w = exited ? (double)n : -(double)n - 1.0;
+    reinterpret_cast<double4 *>(rec)[t] = r;
+}
+
 struct DirPayArgs {
     int64_t total;
     double dtd;
     FieldArg g;
-    const double *exitp;
-    const double *integ;
-    const double *nsteps;
-    const unsigned char *capped;
+    const double *rec;       // the walk's exit records (DirArgs::rec)
+    unsigned char *capped;   // [total] written here: 1 for a capped path
     double *pay;
     double *tau;    // [total] exit time nsteps * dt
     double *paths;  // nullable

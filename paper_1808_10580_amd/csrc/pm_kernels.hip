@@ -398,17 +398,20 @@ __global__ __launch_bounds__(256) void k_dir_payoff(const DirPayArgs a)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.total) return;
-    const double ex = a.exitp[2 * t], ey = a.exitp[2 * t + 1];
-    const bool capped = a.capped[t] != 0;
-    const double pay = (capped ? 0.0 : field_eval(a.g, ex, ey)) - a.integ[t];
+    const double4 r = reinterpret_cast<const double4 *>(a.rec)[t];
+    const double ex = r.x, ey = r.y;
+    const bool capped = r.w < 0.0;
+    const double steps = capped ? -r.w - 1.0 : r.w;
+    const double pay = (capped ? 0.0 : field_eval(a.g, ex, ey)) - r.z;
     a.pay[t] = pay;
-    a.tau[t] = a.nsteps[t] * a.dtd;
+    a.tau[t] = steps * a.dtd;
+    a.capped[t] = capped ? 1 : 0;
     if (a.paths) {
         double *P = a.paths + 4 * t;
         P[0] = ex;
         P[1] = ey;
         P[2] = pay;
-        P[3] = a.nsteps[t];
+        P[3] = steps;
     }
     if (capped) atomicOr(a.flags, PM_FLAG_CAPPED);
     if (!isfinite(pay)) atomicOr(a.flags, PM_FLAG_NONFINITE);

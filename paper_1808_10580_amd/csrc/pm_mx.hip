@@ -885,11 +885,7 @@ __global__ __launch_bounds__(256) void k_dirichlet_tail(const DirArgs<float> a, 
         // every lane writes the same record: no lane-0 branch at the end of the
         // loop, which the compiler could merge with the next walker's lane-0
         // fetch and so split the wave around the shuffle
-        a.exitp[2 * t] = ex;
-        a.exitp[2 * t + 1] = ey;
-        a.integ[t] = I;
-        a.nsteps[t] = (double)n;
-        a.capped[t] = out ? 0 : 1;
+        write_exit_record(a.rec, t, ex, ey, I, n, out);
     }
 }
 

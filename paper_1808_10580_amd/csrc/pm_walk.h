@@ -45,11 +45,7 @@ __device__ __forceinline__ void dirichlet_walk(const DirArgs<T> &a, const StepCo
     uint32_t pi = 0, pj = 0;
 
     auto finish = [&](double ex, double ey, bool exited) {
-        a.exitp[2 * t] = ex;
-        a.exitp[2 * t + 1] = ey;
-        a.integ[t] = I;
-        a.nsteps[t] = (double)n;
-        a.capped[t] = exited ? 0 : 1;
+        write_exit_record(a.rec, t, ex, ey, I, n, exited);
         if constexpr (FK == 2) {
 #pragma unroll
             for (int q = 0; q < PM_MAX_SOURCES; ++q)
