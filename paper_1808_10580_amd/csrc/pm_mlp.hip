@@ -81,27 +81,61 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs g)
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16 zero = (bf16)0.0f;
 
+    // 16-byte loads (8 bf16 along the contiguous dimension, one per thread
+    // per operand tile) where a whole tile is in range and the rows are
+    // 16-byte aligned; element loads otherwise
+    const bool a_vec = bm + TM <= g.M && g.lda % 8 == 0 && (reinterpret_cast<uintptr_t>(g.A) & 15) == 0;
+    const bool b_vec = bn + TN <= g.N && g.ldb % 8 == 0 && (reinterpret_cast<uintptr_t>(g.B) & 15) == 0;
     for (int k0 = kb; k0 < ke; k0 += TK) {
-        // op(A)(m, k) -> As[m][k]; the fastest-varying thread index follows
-        // the contiguous global dimension.
-        for (int e = tid; e < TM * TK; e += 256) {
-            int r, kk;
-            if (!TA) { r = e / TK; kk = e % TK; }
-            else { kk = e / TM; r = e % TM; }
-            const int m = bm + r, k = k0 + kk;
-            bf16 v = zero;
-            if (m < g.M && k < ke) v = TA ? g.A[(int64_t)k * g.lda + m] : g.A[(int64_t)m * g.lda + k];
-            As[r][kk] = v;
+        const bool full_k = k0 + TK <= ke && k0 % 8 == 0;
+        if (a_vec && full_k) {
+            if (!TA) {  // A[m][k]: 8 consecutive k of row m -> one LDS row segment
+                const int r = tid >> 2, kk = 8 * (tid & 3);
+                *reinterpret_cast<uint4 *>(&As[r][kk]) =
+                    *reinterpret_cast<const uint4 *>(g.A + (int64_t)(bm + r) * g.lda + k0 + kk);
+            } else {  // A[k][m]: 8 consecutive m of row k -> column kk of 8 LDS rows
+                const int kk = tid >> 3, r = 8 * (tid & 7);
+                const uint4 v = *reinterpret_cast<const uint4 *>(g.A + (int64_t)(k0 + kk) * g.lda + bm + r);
+                const bf16 *h = reinterpret_cast<const bf16 *>(&v);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) As[r + i][kk] = h[i];
+            }
+        } else {
+            // op(A)(m, k) -> As[m][k]; the fastest-varying thread index
+            // follows the contiguous global dimension.
+            for (int e = tid; e < TM * TK; e += 256) {
+                int r, kk;
+                if (!TA) { r = e / TK; kk = e % TK; }
+                else { kk = e / TM; r = e % TM; }
+                const int m = bm + r, k = k0 + kk;
+                bf16 v = zero;
+                if (m < g.M && k < ke) v = TA ? g.A[(int64_t)k * g.lda + m] : g.A[(int64_t)m * g.lda + k];
+                As[r][kk] = v;
+            }
         }
-        // op(B)(k, n) -> Bs[n][k]
-        for (int e = tid; e < TN * TK; e += 256) {
-            int c, kk;
-            if (!TB) { kk = e / TN; c = e % TN; }
-            else { c = e / TK; kk = e % TK; }
-            const int n = bn + c, k = k0 + kk;
-            bf16 v = zero;
-            if (n < g.N && k < ke) v = TB ? g.B[(int64_t)n * g.ldb + k] : g.B[(int64_t)k * g.ldb + n];
-            Bs[c][kk] = v;
+        if (b_vec && full_k) {
+            if (TB) {  // B[n][k]: 8 consecutive k of row n -> one LDS row segment
+                const int c = tid >> 2, kk = 8 * (tid & 3);
+                *reinterpret_cast<uint4 *>(&Bs[c][kk]) =
+                    *reinterpret_cast<const uint4 *>(g.B + (int64_t)(bn + c) * g.ldb + k0 + kk);
+            } else {  // B[k][n]: 8 consecutive n of row k -> column kk of 8 LDS rows
+                const int kk = tid >> 3, c = 8 * (tid & 7);
+                const uint4 v = *reinterpret_cast<const uint4 *>(g.B + (int64_t)(k0 + kk) * g.ldb + bn + c);
+                const bf16 *h = reinterpret_cast<const bf16 *>(&v);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) Bs[c + i][kk] = h[i];
+            }
+        } else {
+            // op(B)(k, n) -> Bs[n][k]
+            for (int e = tid; e < TN * TK; e += 256) {
+                int c, kk;
+                if (!TB) { kk = e / TN; c = e % TN; }
+                else { c = e / TK; kk = e % TK; }
+                const int n = bn + c, k = k0 + kk;
+                bf16 v = zero;
+                if (n < g.N && k < ke) v = TB ? g.B[(int64_t)n * g.ldb + k] : g.B[(int64_t)k * g.ldb + n];
+                Bs[c][kk] = v;
+            }
         }
         __syncthreads();
         const int fr = lane & 15, fk = 8 * (lane >> 4);
