@@ -339,6 +339,8 @@ def bench_other(args):
     ctx.set_velocity_engine(args.engine)
     if args.dir_tail >= 0:
         ctx.set_dirichlet_tail(args.dir_tail, args.dir_hand)
+    if args.dir_bpc > 0:
+        ctx.set_dirichlet_blocks_per_cu(args.dir_bpc)
     name = args.workload
     cpu = None
     calibration_copy(torch, dev, args.copy_mib)
@@ -610,6 +612,8 @@ def main():
     ap.add_argument("--dir-tail", type=int, default=-1,
                     help="disk walk: live lanes below which waves hand their walkers to the cooperative tail "
                          "(0 = off, -1 = library default)")
+    ap.add_argument("--dir-bpc", type=int, default=0,
+                    help="disk walk: persistent blocks per compute unit (0 = library default)")
     ap.add_argument("--dir-hand", type=int, default=0,
                     help="disk walk: step count at which walkers move to the cooperative tail (0 = off; "
                          "used with --dir-tail >= 0)")
