@@ -372,6 +372,28 @@ def test_tail_capped_walkers_and_sources(pm, ctx, orc, engine_of, tail_of):
     assert stats[64][2] <= max(2 * stats[0][2], 1e-5)
 
 
+def test_tail_general_source(pm, ctx, orc, engine_of, tail_of):
+    """A source of a general field kind (a periodised Gaussian bump) takes the
+    general-field path of both the matrix-core walk and the tail (the field
+    evaluated in FP64 at the left point of every step).  With every wave
+    handing its walkers over (threshold 64) the paths and payoffs match the
+    oracle as closely as without the tail."""
+    engine_of("mfma")
+    f = W.fld("gauss_periodic", [0.2, 0.1, 0.3, 1.0])
+    stats = {}
+    for lb in (0, 64):
+        tail_of(lb)
+        out, st, ref = _run_both(pm, ctx, orc, "fp32", Np=300, kappa=0.05, f=f, scale=0.01)
+        assert st == pm.PM_OK
+        n_tail = ctx.dirichlet_tail_walkers()
+        stats[lb] = _path_stats(np_(out["paths"]), ref)
+        print("general source, tail %d: %d walkers in the tail; different exit steps %.4f; exit p99 %.2e; "
+              "payoff p99 %.2e" % (lb, n_tail, *stats[lb]))
+        assert (n_tail > 0) == (lb > 0)
+    assert stats[64][0] <= stats[0][0] + 0.01
+    assert stats[64][2] <= max(2 * stats[0][2], 1e-5)
+
+
 def test_tail_hand_over_by_step_count_is_reproducible(pm, ctx, engine_of, tail_of):
     """Hand-over at a fixed step count depends on each walker's own steps:
     two calls give the same paths bit for bit, and a walker whose walk is
